@@ -1,0 +1,191 @@
+/*
+ * hnsearch: exact top-1 inner-product search over hierarchically normalised
+ * (HN) vectors on AMD Instinct MI355X (gfx950).
+ *
+ * The method (Sections 3.1-3.3 of "Exact and Deterministic Patch Descriptor
+ * Retrieval via Hierarchical Normalization"): every D = 128 vector carries a
+ * K-dim major prefix of norm sqrt(1-alpha) and a (D-K)-dim minor part of norm
+ * sqrt(alpha) (Eq. 1).  By Eq. 2 and Cauchy-Schwarz (Eq. 3) the full inner
+ * product is at most dot_K + alpha, so after one major-prefix scan only the
+ * entries whose bound reaches a known similarity need the full product
+ * (Algorithm 1).  The result equals exhaustive search (Theorem 1) and is
+ * deterministic (Theorem 2).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named "device" are device memory owned by the caller; they must
+ *    stay valid until the work enqueued on `stream` has completed.  Host
+ *    pointers are read or written before the call returns.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *    enqueued asynchronously unless stated otherwise.
+ *  - Every function returns HN_OK (0) or a negative hn_status and never
+ *    throws.  On error no output is written and hn_last_error() returns a
+ *    message for the calling thread.
+ *  - Indices are 0-based int64 positions in the database as given to the
+ *    build; ties in similarity go to the smallest index.
+ *  - Similarities are the canonical float64 sim: acc = 0; for j = 0..127:
+ *    acc += (double)q[j] * (double)x[j], ascending j, round-to-nearest.
+ */
+#ifndef HNSEARCH_H
+#define HNSEARCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hn_index hn_index; /* opaque; owns its device copies */
+
+typedef enum {
+    HN_OK = 0,
+    HN_ERR_INVALID_ARG = -1,  /* bad size, pointer or option */
+    HN_ERR_NOT_NORMALIZED = -2, /* a row violates the HN block norms (Eq. 1) */
+    HN_ERR_OOM = -3,          /* device allocation failed */
+    HN_ERR_DEVICE = -4,       /* a HIP call failed */
+    HN_ERR_UNSUPPORTED = -5   /* valid but not implemented (e.g. n >= 2^31) */
+} hn_status;
+
+/* Scan precision of the major-prefix pass. */
+enum { HN_PREC_FP32 = 0, HN_PREC_BF16 = 1, HN_PREC_FP8 = 2 };
+
+/* Seed that sets each query's initial lower bound. */
+enum { HN_SEED_PLAIN = 0, HN_SEED_LEARNED = 1 };
+
+/* Build flags. */
+enum {
+    HN_BUILD_NO_VALIDATE = 1u << 0, /* skip the block-norm check (bounds stay
+                                       rigorous: they use measured norms) */
+    HN_BUILD_LOW_PRECISION = 1u << 1 /* also build the BF16 and FP8 copies */
+};
+
+typedef struct {
+    int32_t precision;    /* HN_PREC_*; FP32 by default */
+    int32_t seed;         /* HN_SEED_*; plain by default */
+    int32_t query_tiles;  /* 16-query MFMA tiles per wave; 0 = tuned */
+    int32_t chunk_blocks; /* 16-entry blocks per work-group; 0 = tuned */
+    int64_t survivor_cap; /* capacity of the survivor list in (query, entry)
+                             pairs; 0 = automatic.  Queries whose survivors
+                             do not fit are finished by an exact fallback. */
+    double beta;          /* < 0: exact search (bound alpha).  0 <= beta <
+                             alpha: soft mode of Section 7, which replaces
+                             alpha by beta in the skip test and is no longer
+                             exact. */
+} hn_search_opts;
+
+/* Optional per-query device outputs (any member may be NULL). */
+typedef struct {
+    int64_t *seed_idx;  /* seed entry b (plain seed)                        */
+    double *seed_sim;   /* L_q: the seed's canonical sim (initial bound)    */
+    float *threshold;   /* T_q: survivor test on the scan is s~ >= T_q      */
+    int32_t *survivors; /* entries that passed the first-pass filter        */
+    double *slack;      /* eps_q: rounding slack used for the bound         */
+} hn_search_aux;
+
+/* Host-side totals of one call (filled after the call synchronises). */
+typedef struct {
+    int64_t survivors;        /* sum over queries of first-pass survivors  */
+    int64_t overflow_queries; /* queries finished by the exact fallback    */
+} hn_search_stats;
+
+/*
+ * Build an index over n HN-normalised vectors (Eq. 1, Section 3.1).
+ *   db     device, float32 [n][d] row-major (d must be 128).  Copied; the
+ *          caller may free it once the call returns (the call synchronises).
+ *   k      major prefix length, 1 <= k <= 127.
+ *   alpha  minor energy, 0 <= alpha < 1.
+ *   flags  HN_BUILD_* bits.
+ *   out    receives the index; release it with hn_free_index.
+ * Validation: every row must satisfy | ||x[:k]|| - sqrt(1-alpha) | <=
+ * 2^-13 sqrt(1-alpha) and | ||x[k:]|| - sqrt(alpha) | <= 2^-13 sqrt(alpha)
+ * (alpha = 0: ||x[k:]|| <= 2^-20), with finite entries, else
+ * HN_ERR_NOT_NORMALIZED.  Exactness does not depend on this tolerance: the
+ * bound slack uses the measured block-norm maxima.
+ */
+int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, double alpha,
+                   uint32_t flags, void *stream, hn_index **out);
+
+void hn_free_index(hn_index *ix);
+
+/* Index properties (host outputs, any may be NULL).  norms[3] receives the
+ * rigorous upper bounds {max ||x[:k]||, max ||x[k:]||, max ||x||}. */
+int hn_index_info(const hn_index *ix, int64_t *n, int32_t *k, double *alpha,
+                  double *norms);
+
+/*
+ * Exact top-1 for q queries (Algorithm 1, Section 3.3, as a GPU pipeline):
+ * a major-prefix scan finds each query's seed b (largest scan score, smallest
+ * index on ties); its canonical sim L_q is the initial bound; a second scan
+ * keeps the entries with s~ >= T_q = round_down_f32(L_q - alpha - eps_q),
+ * where eps_q covers the scan's rounding, the float32 storage of the norms
+ * and the float64 evaluation (Eq. 3 made admissible in floating point); the
+ * survivors are rescored in float64 and reduced by the key (sim desc, index
+ * asc).
+ *   queries  device, float32 [q][128]; q >= 0 (q = 0 is a no-op).
+ *   out_idx  device, int64 [q];  out_sim  device, double [q].
+ *   opts     NULL = defaults.  aux, stats: NULL allowed; a non-NULL stats
+ *            makes the call synchronise `stream`.
+ * A query with a non-finite component gets idx -1 and sim NaN.
+ */
+int hn_search_top1(const hn_index *ix, const float *queries, int64_t q, int64_t *out_idx,
+                   double *out_sim, const hn_search_opts *opts, const hn_search_aux *aux,
+                   hn_search_stats *stats, void *stream);
+
+/*
+ * The survivor set of the bound test for given lower bounds (Algorithm 1's
+ * skip test against a fixed s_best, Eq. 3):
+ *   { (q, i) : s~(q, i) >= round_down_f32(L[q] - alpha - eps_q) }.
+ *   lower    device, double [q]: L per query.
+ *   pairs    device, int32 [cap][2]: (query, entry) pairs, unordered.
+ *   count    host, receives the total number of survivors (may exceed cap;
+ *            only the first cap are written).  The call synchronises.
+ *   slack    device, double [q] or NULL: receives eps_q.
+ */
+int hn_filter_survivors(const hn_index *ix, const float *queries, int64_t q,
+                        const double *lower, int32_t *pairs, int64_t cap, int64_t *count,
+                        double *slack, const hn_search_opts *opts, void *stream);
+
+/*
+ * Phase 1 of Algorithm 1 with its score buffer: the scan scores
+ * s~(q, i) = dot_K(q, x_i) (Eq. 2) as the search kernels compute them, for
+ * every query and entry.
+ *   precision  HN_PREC_FP32 or HN_PREC_BF16 (operands rounded to nearest).
+ *   scores     device, float32 [q][n] row-major.
+ */
+int hn_scan_scores(const hn_index *ix, const float *queries, int64_t q, int32_t precision,
+                   float *scores, void *stream);
+
+/*
+ * Exhaustive GPU top-1 over raw vectors (the paper's brute-force 128-dim
+ * baseline, Section 6.2): a float32 scan of all n x 128 products with the
+ * running maximum, then float64 rescoring of every candidate within the
+ * float32 error band of the maximum, so the result is exact.
+ *   db       device, float32 [n][d] (d = 128), any values (finite).
+ *   queries  device, float32 [q][d].
+ *   out_idx, out_sim  device [q].
+ */
+int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const float *queries,
+                       int64_t q, int64_t *out_idx, double *out_sim, void *stream);
+
+/*
+ * Kernel timing for measurement.  Between hn_profile_begin(stream) and
+ * hn_profile_end(stream, ...) every kernel this library enqueues on `stream`
+ * is bracketed by HIP events (enqueued asynchronously, no synchronisation).
+ * hn_profile_end synchronises `stream`, sums the elapsed times per kernel
+ * name and ends the session.
+ *   names   host, receives up to `max` pointers to static kernel names.
+ *   ms      host double [max]: total milliseconds per kernel name.
+ *   counts  host int64 [max]: launches per kernel name.
+ *   n_out   host, receives the number of distinct kernel names.
+ */
+int hn_profile_begin(void *stream);
+int hn_profile_end(void *stream, const char **names, double *ms, int64_t *counts, int32_t max,
+                   int32_t *n_out);
+
+/* Message for the calling thread's last non-OK status ("" if none). */
+const char *hn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HNSEARCH_H */

@@ -80,10 +80,12 @@ def lib():
 
 
 def default_threads() -> int:
+    """Host threads to use: the CPUs this process may run on, at most 16."""
     try:
-        return max(1, len(os.sched_getaffinity(0)))
+        n = len(os.sched_getaffinity(0))
     except AttributeError:
-        return max(1, os.cpu_count() or 1)
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
 
 
 def _f32(a):

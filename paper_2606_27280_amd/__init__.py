@@ -1,1 +1,196 @@
-"""HN exact top-1 search on MI355X (see hnsearch.h for the C ABI)."""
+"""Exact top-1 inner-product search over HN vectors on MI355X.
+
+Thin binding over libhnsearch (include/hnsearch.h): torch tensors provide
+device memory and the current HIP stream; every step of the search runs in the
+library's HIP kernels.  Importing this package does not load the library; the
+first call does, and it raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (HN_BUILD_LOW_PRECISION, HN_BUILD_NO_VALIDATE, HN_PREC_BF16,
+                   HN_PREC_FP8, HN_PREC_FP32, HN_SEED_LEARNED, HN_SEED_PLAIN, HNError)
+
+__all__ = ["Index", "bruteforce_top1", "profile", "HNError", "PRECISIONS", "HN_PREC_FP32",
+           "HN_PREC_BF16", "HN_PREC_FP8", "HN_SEED_PLAIN", "HN_SEED_LEARNED",
+           "HN_BUILD_NO_VALIDATE", "HN_BUILD_LOW_PRECISION"]
+
+PRECISIONS = {"fp32": HN_PREC_FP32, "bf16": HN_PREC_BF16, "fp8": HN_PREC_FP8}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name, ndim=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA/HIP tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must have dtype %s (got %s)" % (name, dtype, t.dtype))
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError("%s must have %d dimensions" % (name, ndim))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _opts(precision="fp32", query_tiles=0, chunk_blocks=0, survivor_cap=0, beta=None,
+          seed="plain"):
+    o = _lib.SearchOpts()
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.seed = {"plain": HN_SEED_PLAIN, "learned": HN_SEED_LEARNED}[seed] if isinstance(seed, str) else int(seed)
+    o.query_tiles = int(query_tiles)
+    o.chunk_blocks = int(chunk_blocks)
+    o.survivor_cap = int(survivor_cap)
+    o.beta = -1.0 if beta is None else float(beta)
+    return o
+
+
+class Index:
+    """hn_build_index / hn_search_top1 / hn_filter_survivors / hn_scan_scores."""
+
+    def __init__(self, db, k: int, alpha: float, flags: int = 0, stream=None):
+        torch = _torch()
+        L = _lib.lib()
+        dp = _dev(db, torch.float32, "db", 2)
+        h = ctypes.c_void_p()
+        _lib.check(L.hn_build_index(dp, db.shape[0], db.shape[1], int(k), float(alpha),
+                                    int(flags), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.n = int(db.shape[0])
+        self.k = int(k)
+        self.alpha = float(alpha)
+        self.device = db.device
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().hn_free_index(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self):
+        n, k, a = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_double()
+        norms = (ctypes.c_double * 3)()
+        _lib.check(_lib.lib().hn_index_info(self._h, ctypes.byref(n), ctypes.byref(k),
+                                            ctypes.byref(a), norms))
+        return {"n": n.value, "k": k.value, "alpha": a.value, "norms": tuple(norms)}
+
+    def search(self, queries, precision="fp32", query_tiles=0, chunk_blocks=0,
+               survivor_cap=0, beta=None, aux=False, stats=False, stream=None, out=None):
+        """Exact top-1 per query: (idx int64 [q], sim float64 [q]) plus the
+        auxiliary outputs (dict) and/or the call's stats when requested."""
+        torch = _torch()
+        qp = _dev(queries, torch.float32, "queries", 2)
+        q = queries.shape[0]
+        if out is None:
+            idx = torch.empty(q, dtype=torch.int64, device=queries.device)
+            sim = torch.empty(q, dtype=torch.float64, device=queries.device)
+        else:
+            idx, sim = out
+        o = _opts(precision, query_tiles, chunk_blocks, survivor_cap, beta)
+        a = None
+        auxd = None
+        if aux:
+            dev = queries.device
+            auxd = {"seed_idx": torch.empty(q, dtype=torch.int64, device=dev),
+                    "seed_sim": torch.empty(q, dtype=torch.float64, device=dev),
+                    "threshold": torch.empty(q, dtype=torch.float32, device=dev),
+                    "survivors": torch.empty(q, dtype=torch.int32, device=dev),
+                    "slack": torch.empty(q, dtype=torch.float64, device=dev)}
+            a = _lib.SearchAux(*[_ptr(auxd[f]) for f, _ in _lib.SearchAux._fields_])
+        st = _lib.SearchStats() if stats else None
+        _lib.check(_lib.lib().hn_search_top1(
+            self._h, qp, q, _ptr(idx), _ptr(sim), ctypes.byref(o),
+            ctypes.byref(a) if a is not None else None,
+            ctypes.byref(st) if st is not None else None, _stream(stream)))
+        res = [idx, sim]
+        if aux:
+            res.append(auxd)
+        if stats:
+            res.append({"survivors": st.survivors, "overflow_queries": st.overflow_queries})
+        return tuple(res)
+
+    def filter_survivors(self, queries, lower, cap, precision="fp32", beta=None, stream=None):
+        """Pairs (query, entry) with scan score >= round_down(L - alpha - eps);
+        returns (pairs int32 [min(count,cap)][2], count, slack float64 [q])."""
+        torch = _torch()
+        qp = _dev(queries, torch.float32, "queries", 2)
+        lp = _dev(lower, torch.float64, "lower", 1)
+        q = queries.shape[0]
+        pairs = torch.empty((max(int(cap), 1), 2), dtype=torch.int32, device=queries.device)
+        slack = torch.empty(q, dtype=torch.float64, device=queries.device)
+        cnt = ctypes.c_int64()
+        o = _opts(precision, beta=beta)
+        _lib.check(_lib.lib().hn_filter_survivors(self._h, qp, q, lp, _ptr(pairs), int(cap),
+                                                  ctypes.byref(cnt), _ptr(slack),
+                                                  ctypes.byref(o), _stream(stream)))
+        return pairs[: min(cnt.value, int(cap))], cnt.value, slack
+
+    def scan_scores(self, queries, precision="fp32", stream=None):
+        torch = _torch()
+        qp = _dev(queries, torch.float32, "queries", 2)
+        q = queries.shape[0]
+        out = torch.empty((q, self.n), dtype=torch.float32, device=queries.device)
+        p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        _lib.check(_lib.lib().hn_scan_scores(self._h, qp, q, p, _ptr(out), _stream(stream)))
+        return out
+
+
+class profile:
+    """Context manager over hn_profile_begin / hn_profile_end: per-kernel
+    total milliseconds and launch counts for kernels enqueued on `stream`."""
+
+    def __init__(self, stream=None):
+        self.stream = stream
+        self.result = {}
+
+    def __enter__(self):
+        _lib.check(_lib.lib().hn_profile_begin(_stream(self.stream)))
+        return self
+
+    def __exit__(self, *exc):
+        mx = 64
+        names = (ctypes.c_char_p * mx)()
+        ms = (ctypes.c_double * mx)()
+        cnt = (ctypes.c_int64 * mx)()
+        n = ctypes.c_int32()
+        _lib.check(_lib.lib().hn_profile_end(_stream(self.stream), names, ms, cnt, mx,
+                                             ctypes.byref(n)))
+        self.result = {names[i].decode(): {"ms": ms[i], "launches": cnt[i]}
+                       for i in range(n.value)}
+        return False
+
+
+def bruteforce_top1(db, queries, stream=None, out=None):
+    """Exhaustive exact top-1 (hn_bruteforce_top1): (idx int64, sim float64)."""
+    torch = _torch()
+    dp = _dev(db, torch.float32, "db", 2)
+    qp = _dev(queries, torch.float32, "queries", 2)
+    q = queries.shape[0]
+    if out is None:
+        idx = torch.empty(q, dtype=torch.int64, device=queries.device)
+        sim = torch.empty(q, dtype=torch.float64, device=queries.device)
+    else:
+        idx, sim = out
+    _lib.check(_lib.lib().hn_bruteforce_top1(dp, db.shape[0], db.shape[1], qp, q, _ptr(idx),
+                                             _ptr(sim), _stream(stream)))
+    return idx, sim

@@ -1,0 +1,94 @@
+"""ctypes declarations of the libhnsearch C ABI (include/hnsearch.h).
+
+Only argument marshalling lives here.  Loading fails loudly when the HIP
+library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhnsearch.so")
+
+HN_OK = 0
+HN_ERR_INVALID_ARG = -1
+HN_ERR_NOT_NORMALIZED = -2
+HN_ERR_OOM = -3
+HN_ERR_DEVICE = -4
+HN_ERR_UNSUPPORTED = -5
+
+HN_PREC_FP32, HN_PREC_BF16, HN_PREC_FP8 = 0, 1, 2
+HN_SEED_PLAIN, HN_SEED_LEARNED = 0, 1
+HN_BUILD_NO_VALIDATE = 1 << 0
+HN_BUILD_LOW_PRECISION = 1 << 1
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_u32 = ctypes.c_uint32
+_dbl = ctypes.c_double
+
+
+class SearchOpts(ctypes.Structure):
+    _fields_ = [("precision", _i32), ("seed", _i32), ("query_tiles", _i32),
+                ("chunk_blocks", _i32), ("survivor_cap", _i64), ("beta", _dbl)]
+
+
+class SearchAux(ctypes.Structure):
+    _fields_ = [("seed_idx", _vp), ("seed_sim", _vp), ("threshold", _vp),
+                ("survivors", _vp), ("slack", _vp)]
+
+
+class SearchStats(ctypes.Structure):
+    _fields_ = [("survivors", _i64), ("overflow_queries", _i64)]
+
+
+class HNError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("hnsearch error %d: %s" % (code, msg))
+        self.code = code
+
+
+# name -> (restype, argtypes); every symbol include/hnsearch.h declares
+SIGNATURES = {
+    "hn_build_index": (_i32, [_vp, _i64, _i32, _i32, _dbl, _u32, _vp, ctypes.POINTER(_vp)]),
+    "hn_free_index": (None, [_vp]),
+    "hn_index_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i32),
+                             ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
+    "hn_search_top1": (_i32, [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(SearchOpts),
+                              ctypes.POINTER(SearchAux), ctypes.POINTER(SearchStats), _vp]),
+    "hn_filter_survivors": (_i32, [_vp, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp,
+                                   ctypes.POINTER(SearchOpts), _vp]),
+    "hn_scan_scores": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp]),
+    "hn_bruteforce_top1": (_i32, [_vp, _i64, _i32, _vp, _i64, _vp, _vp, _vp]),
+    "hn_profile_begin": (_i32, [_vp]),
+    "hn_profile_end": (_i32, [_vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_dbl),
+                              ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32)]),
+    "hn_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libhnsearch.so (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libhnsearch.so is not built (expected at %s); run "
+                "`python -c 'import __graft_entry__ as g; g.build()'`" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != HN_OK:
+        msg = lib().hn_last_error()
+        raise HNError(rc, msg.decode() if msg else "")

@@ -1,0 +1,310 @@
+// Index build: block-norm validation (Eq. 1), rigorous norm maxima for the
+// bound slack (Eq. 3), and the device copies the search streams.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+#include <unordered_map>
+
+#include "hn_internal.h"
+
+namespace hn {
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+void clear_error() { g_err[0] = 0; }
+
+// ---------------------------------------------------------------- arenas
+
+namespace {
+struct ArenaKey {
+    int device;
+    void *stream;
+    bool operator==(const ArenaKey &o) const { return device == o.device && stream == o.stream; }
+};
+struct ArenaKeyHash {
+    size_t operator()(const ArenaKey &k) const {
+        return std::hash<void *>()(k.stream) * 31u + (size_t)k.device;
+    }
+};
+std::mutex g_arena_mu;
+std::unordered_map<ArenaKey, Arena *, ArenaKeyHash> g_arenas;
+}  // namespace
+
+int arena_for(void *stream, size_t bytes, Arena **out) {
+    int dev = 0;
+    HN_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    Arena *&a = g_arenas[ArenaKey{dev, stream}];
+    if (!a) a = new (std::nothrow) Arena();
+    if (!a) return fail(HN_ERR_OOM, "host allocation failed");
+    if (a->cap < bytes) {
+        if (a->base) {
+            // the old buffer may still be in use by work queued on the stream
+            HN_HIP(hipStreamSynchronize((hipStream_t)stream));
+            HN_HIP(hipFree(a->base));
+            a->base = nullptr;
+            a->cap = 0;
+        }
+        size_t want = bytes + bytes / 4 + (1u << 20);
+        if (hipMalloc(&a->base, want) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(HN_ERR_OOM, "scratch allocation of %zu bytes failed", want);
+        }
+        a->cap = want;
+    }
+    a->used = 0;
+    *out = a;
+    return HN_OK;
+}
+
+// --------------------------------------------------------------- kernels
+
+namespace {
+
+struct BuildStats {
+    unsigned long long key_major, key_minor, key_full;  // max block norms
+    unsigned long long key_major16, key_res16;          // bf16 copy
+    unsigned long long bad_rows, nonfinite_rows;
+    long long first_bad;
+};
+
+__global__ void build_stats_init(BuildStats *s) {
+    if (threadIdx.x == 0) {
+        s->key_major = s->key_minor = s->key_full = 0;
+        s->key_major16 = s->key_res16 = 0;
+        s->bad_rows = s->nonfinite_rows = 0;
+        s->first_bad = 0x7fffffffffffffffll;
+    }
+}
+
+__device__ __forceinline__ float bf16_round(float f) {
+    // round-to-nearest-even onto the 8-bit bfloat16 significand
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = sh[0];
+    for (int w = 1; w < NT / 64; ++w) r = fmax(r, sh[w]);
+    __syncthreads();
+    return r;
+}
+
+// One thread per row: float64 block norms, the Eq. 1 check, and the maxima.
+__global__ __launch_bounds__(256) void build_norms(const float *__restrict__ db, int64_t n,
+                                                   int k, double alpha, BuildStats *st) {
+    __shared__ double sh[4];
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double nM = 0, nm = 0, nf = 0, nM16 = 0, r16 = 0;
+    if (i < n) {
+        const float *x = db + i * kDim;
+        double sM = 0, sm = 0, s16 = 0, sr = 0;
+        bool finite = true;
+        for (int j = 0; j < kDim; ++j) {
+            float v = x[j];
+            finite = finite && isfinite(v);
+            double dv = (double)v;
+            if (j < k) {
+                sM = fma(dv, dv, sM);
+                double b = (double)bf16_round(v);
+                s16 = fma(b, b, s16);
+                sr = fma(b - dv, b - dv, sr);
+            } else {
+                sm = fma(dv, dv, sm);
+            }
+        }
+        nM = sqrt(sM);
+        nm = sqrt(sm);
+        nf = sqrt(sM + sm);
+        nM16 = sqrt(s16);
+        r16 = sqrt(sr);
+        const double tol = ldexp(1.0, -13);
+        double cM = sqrt(1.0 - alpha), cm = sqrt(alpha);
+        bool ok = finite && fabs(nM - cM) <= tol * cM &&
+                  (alpha > 0.0 ? fabs(nm - cm) <= tol * cm : nm <= ldexp(1.0, -20));
+        if (!ok) {
+            atomicAdd(&st->bad_rows, 1ull);
+            atomicMin(&st->first_bad, (long long)i);
+        }
+        if (!finite) {
+            atomicAdd(&st->nonfinite_rows, 1ull);
+            nM = nm = nf = nM16 = r16 = 0;
+        }
+    }
+    double a = block_max<256>(nM, sh);
+    double b = block_max<256>(nm, sh);
+    double c = block_max<256>(nf, sh);
+    double d = block_max<256>(nM16, sh);
+    double e = block_max<256>(r16, sh);
+    if (threadIdx.x == 0) {
+        atomicMax(&st->key_major, key_of(a));
+        atomicMax(&st->key_minor, key_of(b));
+        atomicMax(&st->key_full, key_of(c));
+        atomicMax(&st->key_major16, key_of(d));
+        atomicMax(&st->key_res16, key_of(e));
+    }
+}
+
+// major32[i][c] = x[i][c] for c < k (zero elsewhere and for padded rows).
+__global__ __launch_bounds__(256) void build_major32(const float *__restrict__ db, int64_t n,
+                                                     int64_t n_pad, int k, int kp,
+                                                     float *__restrict__ out) {
+    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_pad * kp) return;
+    int64_t i = t / kp;
+    int c = (int)(t % kp);
+    out[t] = (i < n && c < k) ? db[i * kDim + c] : 0.0f;
+}
+
+__global__ __launch_bounds__(256) void build_major16(const float *__restrict__ db, int64_t n,
+                                                     int64_t n_pad, int k, int kb,
+                                                     uint16_t *__restrict__ out) {
+    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_pad * kb) return;
+    int64_t i = t / kb;
+    int c = (int)(t % kb);
+    float v = (i < n && c < k) ? db[i * kDim + c] : 0.0f;
+    out[t] = (uint16_t)(__float_as_uint(bf16_round(v)) >> 16);
+}
+
+inline unsigned grid_for(int64_t items, int per) { return (unsigned)((items + per - 1) / per); }
+
+double key_to_double_host(unsigned long long k) {
+    unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    double d;
+    memcpy(&d, &b, sizeof d);
+    return d;
+}
+
+// The float64 norm of a float32 row block has relative error well below
+// 2^-40; scaling by (1 + 2^-40) gives a rigorous upper bound.
+double round_up_norm(double v) { return v * (1.0 + ldexp(1.0, -40)); }
+
+void free_index(hn_index *ix) {
+    if (!ix) return;
+    if (ix->rows) (void)hipFree(ix->rows);
+    if (ix->major32) (void)hipFree(ix->major32);
+    if (ix->major16) (void)hipFree(ix->major16);
+    delete ix;
+}
+
+}  // namespace
+}  // namespace hn
+
+using namespace hn;
+
+extern "C" const char *hn_last_error(void) { return hn::g_err; }
+
+extern "C" void hn_free_index(hn_index *ix) {
+    if (!ix) return;
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && cur != ix->device) {
+        (void)hipSetDevice(ix->device);
+        free_index(ix);
+        (void)hipSetDevice(cur);
+        return;
+    }
+    free_index(ix);
+}
+
+extern "C" int hn_index_info(const hn_index *ix, int64_t *n, int32_t *k, double *alpha,
+                             double *norms) {
+    clear_error();
+    if (!ix) return fail(HN_ERR_INVALID_ARG, "null index");
+    if (n) *n = ix->n;
+    if (k) *k = ix->k;
+    if (alpha) *alpha = ix->alpha;
+    if (norms) {
+        norms[0] = ix->mu_major;
+        norms[1] = ix->mu_minor;
+        norms[2] = ix->mu_full;
+    }
+    return HN_OK;
+}
+
+extern "C" int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, double alpha,
+                              uint32_t flags, void *stream, hn_index **out) {
+    clear_error();
+    if (!out) return fail(HN_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (!db) return fail(HN_ERR_INVALID_ARG, "db is null");
+    if (d != kDim) return fail(HN_ERR_INVALID_ARG, "d must be 128 (got %d)", d);
+    if (k < 1 || k > kDim - 1) return fail(HN_ERR_INVALID_ARG, "k must be in [1,127] (got %d)", k);
+    if (!(alpha >= 0.0 && alpha < 1.0)) return fail(HN_ERR_INVALID_ARG, "alpha must be in [0,1)");
+    if (n < 1) return fail(HN_ERR_INVALID_ARG, "n must be >= 1");
+    if (n >= (int64_t)1 << 31) return fail(HN_ERR_UNSUPPORTED, "n must be < 2^31");
+    hipStream_t s = (hipStream_t)stream;
+
+    hn_index *ix = new (std::nothrow) hn_index();
+    if (!ix) return fail(HN_ERR_OOM, "host allocation failed");
+    HN_HIP(hipGetDevice(&ix->device));
+    ix->n = n;
+    ix->n_pad = (n + 63) / 64 * 64;
+    ix->k = k;
+    ix->alpha = alpha;
+    ix->kp = f32_width(k);
+    ix->kb = bf16_width(k);
+
+    BuildStats *st = nullptr;
+    auto cleanup = [&](int code) {
+        if (st) (void)hipFree(st);
+        free_index(ix);
+        return code;
+    };
+    if (hipMalloc(&st, sizeof(BuildStats)) != hipSuccess ||
+        hipMalloc(&ix->rows, (size_t)n * kDim * sizeof(float)) != hipSuccess ||
+        hipMalloc(&ix->major32, (size_t)ix->n_pad * ix->kp * sizeof(float)) != hipSuccess ||
+        hipMalloc(&ix->major16, (size_t)ix->n_pad * ix->kb * sizeof(uint16_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(HN_ERR_OOM, "device allocation failed for n=%lld", (long long)n);
+        return cleanup(HN_ERR_OOM);
+    }
+    hipLaunchKernelGGL(build_stats_init, dim3(1), dim3(64), 0, s, st);
+    hipLaunchKernelGGL(build_norms, dim3(grid_for(n, 256)), dim3(256), 0, s, db, n, k, alpha, st);
+    hipLaunchKernelGGL(build_major32, dim3(grid_for(ix->n_pad * ix->kp, 256)), dim3(256), 0, s,
+                       db, n, ix->n_pad, k, ix->kp, ix->major32);
+    hipLaunchKernelGGL(build_major16, dim3(grid_for(ix->n_pad * ix->kb, 256)), dim3(256), 0, s,
+                       db, n, ix->n_pad, k, ix->kb, ix->major16);
+    hipError_t e = hipMemcpyAsync(ix->rows, db, (size_t)n * kDim * sizeof(float),
+                                  hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    BuildStats h;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, st, sizeof h, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        fail(HN_ERR_DEVICE, "index build: %s", hipGetErrorString(e));
+        return cleanup(HN_ERR_DEVICE);
+    }
+    if (h.nonfinite_rows || (h.bad_rows && !(flags & HN_BUILD_NO_VALIDATE))) {
+        fail(HN_ERR_NOT_NORMALIZED,
+             "%llu rows violate the HN block norms (first bad row %lld)", h.bad_rows,
+             h.first_bad);
+        return cleanup(HN_ERR_NOT_NORMALIZED);
+    }
+    // With HN_BUILD_NO_VALIDATE a finite off-norm row is accepted: the bound
+    // slack uses the measured maxima below, so the search stays exact.
+    ix->mu_major = round_up_norm(key_to_double_host(h.key_major));
+    ix->mu_minor = round_up_norm(key_to_double_host(h.key_minor));
+    ix->mu_full = round_up_norm(key_to_double_host(h.key_full));
+    ix->mu_major16 = round_up_norm(key_to_double_host(h.key_major16));
+    ix->res16 = round_up_norm(key_to_double_host(h.key_res16));
+    (void)hipFree(st);
+    *out = ix;
+    return HN_OK;
+}

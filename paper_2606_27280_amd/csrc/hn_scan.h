@@ -1,0 +1,293 @@
+// Major-prefix scan kernels (the hot loop of Algorithm 1's Phase 1 and of
+// its bound test), written for CDNA4 MFMA.
+//
+// Tile: one wave computes a 16-entry x 16-query block of scan scores with
+// MFMA, entries as the A operand (rows) and queries as the B operand
+// (columns).  Lane l holds scores for query l % 16 and entries 4 (l / 16) +
+// v, v = 0..3.  The K dimension is split across the four 16-lane groups: lane
+// group g reads a contiguous slice of each entry row, so a 16-entry block of
+// a [n][W] stream is one contiguous 16 * W element read per wave.  The dot
+// product is a sum over k and the same k -> (step, lane group) bijection is
+// applied to both operands, so any contiguous slicing gives the same set of
+// products; their summation order inside the MFMA is covered by the scan's
+// rounding slack, never relied upon.
+//
+// Work decomposition: a work-group of 4 waves owns one query block (WQ query
+// sub-blocks of NQ 16-query tiles) and one chunk of entry blocks; the 4 / WQ
+// waves that share a sub-block interleave over the chunk's entry blocks.
+// Work items are laid out so that consecutive items on one XCD (blockIdx % 8)
+// read the same chunk, keeping it in that XCD's L2 while every query block
+// passes over it.
+#pragma once
+
+#include "hn_internal.h"
+
+namespace hn {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+enum ScanMode { kArgmax = 0, kFilter = 1, kWindow = 2, kStore = 3 };
+
+struct ScanArgs {
+    const void *x;      // entry stream, row stride x_stride elements
+    int64_t x_stride;
+    const void *qs;     // query operands, row stride q_stride elements
+    int64_t q_stride;
+    int64_t n;          // valid entries
+    int32_t n_blocks;   // ceil(n / 16)
+    int32_t chunk_blocks, n_chunks;
+    int32_t n_qb, n_items;
+    int32_t q_count, q_pad;
+    float *part_val;    // argmax / window: [n_chunks][q_pad]
+    int32_t *part_idx;  // argmax: smallest entry of the winning 4-entry group
+    const float *thr;   // filter: T_q; window: window width; [q_pad]
+    int2 *pairs;        // filter / window: (query, entry)
+    float *pair_val;    // window: scan score of the pair
+    unsigned long long *counter;
+    int64_t cap;
+    int32_t *qflag;     // set when a query's pair did not fit
+    float *scores;      // store: [q_count][n]
+};
+
+// ------------------------------------------------------------ operand policies
+
+template <int W>  // float32 stream of width W (multiple of 4)
+struct F32Tile {
+    static constexpr int kSlice = W / 4;  // elements per lane group
+    typedef float Elem;
+    struct Frag {
+        float v[kSlice];
+    };
+    __device__ __forceinline__ static void load(Frag &f, const float *p) {
+        if constexpr (kSlice == 1) {
+            f.v[0] = p[0];
+        } else if constexpr (kSlice == 2) {
+            float2 a = *reinterpret_cast<const float2 *>(p);
+            f.v[0] = a.x;
+            f.v[1] = a.y;
+        } else {
+#pragma unroll
+            for (int c = 0; c < kSlice / 4; ++c) {
+                float4 a = reinterpret_cast<const float4 *>(p)[c];
+                f.v[4 * c + 0] = a.x;
+                f.v[4 * c + 1] = a.y;
+                f.v[4 * c + 2] = a.z;
+                f.v[4 * c + 3] = a.w;
+            }
+        }
+    }
+    __device__ __forceinline__ static void zero(Frag &f) {
+#pragma unroll
+        for (int m = 0; m < kSlice; ++m) f.v[m] = 0.0f;
+    }
+    __device__ __forceinline__ static v4f mma(const Frag &x, const Frag &q, v4f acc) {
+#pragma unroll
+        for (int m = 0; m < kSlice; ++m)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.v[m], q.v[m], acc, 0, 0, 0);
+        return acc;
+    }
+};
+
+template <int W>  // bfloat16 stream of width W (16, 32, 64 or 128)
+struct BF16Tile {
+    static constexpr int kSlice = W / 4;
+    typedef uint16_t Elem;
+    struct Frag {
+        uint4 v[(kSlice + 7) / 8];  // kSlice = 4 uses the low half of v[0]
+    };
+    __device__ __forceinline__ static void load(Frag &f, const uint16_t *p) {
+        if constexpr (kSlice == 4) {
+            uint2 a = *reinterpret_cast<const uint2 *>(p);
+            f.v[0] = make_uint4(a.x, a.y, 0u, 0u);
+        } else {
+#pragma unroll
+            for (int c = 0; c < kSlice / 8; ++c) f.v[c] = reinterpret_cast<const uint4 *>(p)[c];
+        }
+    }
+    __device__ __forceinline__ static void zero(Frag &f) {
+#pragma unroll
+        for (int c = 0; c < (kSlice + 7) / 8; ++c) f.v[c] = make_uint4(0u, 0u, 0u, 0u);
+    }
+    __device__ __forceinline__ static v4f mma(const Frag &x, const Frag &q, v4f acc) {
+        if constexpr (kSlice == 4) {
+            v4s a, b;
+            uint2 xa = make_uint2(x.v[0].x, x.v[0].y), qa = make_uint2(q.v[0].x, q.v[0].y);
+            __builtin_memcpy(&a, &xa, 8);
+            __builtin_memcpy(&b, &qa, 8);
+            return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int c = 0; c < kSlice / 8; ++c) {
+                v8bf a, b;
+                __builtin_memcpy(&a, &x.v[c], 16);
+                __builtin_memcpy(&b, &q.v[c], 16);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+            }
+            return acc;
+        }
+    }
+};
+
+// ------------------------------------------------------------ helpers
+
+__device__ __forceinline__ unsigned lane_prefix(unsigned long long m) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// Append the lane's entries with score >= t (predicate per v) to the pair
+// list: one atomic per wave, positions by ballot + mbcnt prefix counts.
+template <bool WithVal>
+__device__ __forceinline__ void emit_pairs(const ScanArgs &A, v4f a, float t, bool qvalid,
+                                           int q, int e0) {
+    bool p0 = qvalid && a[0] >= t, p1 = qvalid && a[1] >= t;
+    bool p2 = qvalid && a[2] >= t, p3 = qvalid && a[3] >= t;
+    unsigned long long m0 = __ballot(p0), m1 = __ballot(p1), m2 = __ballot(p2),
+                       m3 = __ballot(p3);
+    unsigned c0 = __popcll(m0), c1 = __popcll(m1), c2 = __popcll(m2), c3 = __popcll(m3);
+    if (c0 + c1 + c2 + c3 == 0) return;
+    unsigned long long base = 0;
+    if (__lane_id() == 0) base = atomicAdd(A.counter, (unsigned long long)(c0 + c1 + c2 + c3));
+    base = __shfl(base, 0);
+    const bool pv[4] = {p0, p1, p2, p3};
+    const unsigned long long mv[4] = {m0, m1, m2, m3};
+    const unsigned off[4] = {0u, c0, c0 + c1, c0 + c1 + c2};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        if (pv[v]) {
+            unsigned long long pos = base + off[v] + lane_prefix(mv[v]);
+            if ((int64_t)pos < A.cap) {
+                A.pairs[pos] = make_int2(q, e0 + v);
+                if (WithVal) A.pair_val[pos] = a[v];
+            } else {
+                A.qflag[q] = 1;
+            }
+        }
+    }
+}
+
+// Lexicographic (value desc, index asc) merge; idx < 0 marks "none".
+__device__ __forceinline__ void lex_merge(float &v, int &i, float ov, int oi) {
+    if (oi >= 0 && (i < 0 || ov > v || (ov == v && oi < i))) {
+        v = ov;
+        i = oi;
+    }
+}
+
+// ------------------------------------------------------------ the scan kernel
+
+template <class Tile, int NQ, int WQ, int MODE>
+__global__ __launch_bounds__(256) void scan_kernel(ScanArgs A) {
+    typedef typename Tile::Elem Elem;
+    typedef typename Tile::Frag Frag;
+    constexpr int NS = kWaves / WQ;  // waves sharing one query sub-block
+    __shared__ float sh_val[kWaves][NQ * 16];
+    __shared__ int sh_idx[kWaves][NQ * 16];
+
+    const int per_xcd = gridDim.x / kXcds;
+    const int item = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+    if (item >= A.n_items) return;
+    const int chunk = item / A.n_qb, qb = item % A.n_qb;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int g = lane >> 4, r = lane & 15;
+    const int wq = wave % WQ, ws = wave / WQ;
+    const int tile0 = (qb * WQ + wq) * NQ;
+
+    const Elem *xs = reinterpret_cast<const Elem *>(A.x);
+    const Elem *qsrc = reinterpret_cast<const Elem *>(A.qs);
+    Frag qf[NQ];
+    int qid[NQ];
+    float thr[NQ], best[NQ];
+    int bblk[NQ];
+#pragma unroll
+    for (int t = 0; t < NQ; ++t) {
+        qid[t] = (tile0 + t) * 16 + r;
+        if (qid[t] < A.q_count)
+            Tile::load(qf[t], qsrc + (int64_t)qid[t] * A.q_stride + g * Tile::kSlice);
+        else
+            Tile::zero(qf[t]);
+        thr[t] = (MODE == kFilter || MODE == kWindow) ? A.thr[qid[t]] : 0.0f;
+        best[t] = -INFINITY;
+        bblk[t] = -1;
+    }
+
+    const int blk0 = chunk * A.chunk_blocks;
+    const int blk1 = min(blk0 + A.chunk_blocks, A.n_blocks);
+    const int64_t last_row = A.n - 1;
+    for (int blk = blk0 + ws; blk < blk1; blk += NS) {
+        Frag xf;
+        int64_t row = min((int64_t)blk * 16 + r, last_row);
+        Tile::load(xf, xs + row * A.x_stride + g * Tile::kSlice);
+        const int e0 = blk * 16 + 4 * g;
+        const bool tail = (int64_t)(blk + 1) * 16 > A.n;
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = Tile::mma(xf, qf[t], acc);
+            if (tail) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (e0 + v >= A.n) acc[v] = -INFINITY;
+            }
+            const float mx = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
+            if constexpr (MODE == kArgmax) {
+                if (mx > best[t]) {
+                    best[t] = mx;
+                    bblk[t] = blk;
+                }
+            } else if constexpr (MODE == kFilter) {
+                if (__ballot(mx >= thr[t])) emit_pairs<false>(A, acc, thr[t], qid[t] < A.q_count, qid[t], e0);
+            } else if constexpr (MODE == kWindow) {
+                const float nb = fmaxf(best[t], mx);
+                best[t] = nb;
+                const float lim = nb - thr[t];
+                if (__ballot(mx >= lim)) emit_pairs<true>(A, acc, lim, qid[t] < A.q_count, qid[t], e0);
+            } else {
+                if (qid[t] < A.q_count) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (e0 + v < A.n) A.scores[(int64_t)qid[t] * A.n + e0 + v] = acc[v];
+                }
+            }
+        }
+    }
+
+    if constexpr (MODE == kArgmax || MODE == kWindow) {
+        // per query: merge the 4 lane groups, then the NS waves of the sub-block
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            float v = best[t];
+            int i = (MODE == kArgmax) ? (bblk[t] >= 0 ? bblk[t] * 16 + 4 * g : -1)
+                                      : (v > -INFINITY ? 0 : -1);
+#pragma unroll
+            for (int o = 16; o < 64; o <<= 1) {
+                float ov = __shfl_xor(v, o);
+                int oi = __shfl_xor(i, o);
+                lex_merge(v, i, ov, oi);
+            }
+            if (g == 0) {
+                sh_val[wave][t * 16 + r] = v;
+                sh_idx[wave][t * 16 + r] = i;
+            }
+        }
+        __syncthreads();
+        if (ws == 0 && g == 0) {
+#pragma unroll
+            for (int t = 0; t < NQ; ++t) {
+                float v = sh_val[wave][t * 16 + r];
+                int i = sh_idx[wave][t * 16 + r];
+                for (int s = 1; s < NS; ++s)
+                    lex_merge(v, i, sh_val[wave + s * WQ][t * 16 + r], sh_idx[wave + s * WQ][t * 16 + r]);
+                const int q = qid[t];
+                if (q < A.q_pad) {
+                    A.part_val[(int64_t)chunk * A.q_pad + q] = v;
+                    if (MODE == kArgmax) A.part_idx[(int64_t)chunk * A.q_pad + q] = i;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace hn

@@ -1,0 +1,1073 @@
+// Exact top-1 search pipeline (Algorithm 1 on the GPU) and the exhaustive
+// baseline.  Kernels other than the scan itself live here: query preparation,
+// seed selection with the bound slack, float64 rescoring, the deterministic
+// argmax, the exact overflow fallback and the output writer.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "hn_scan.h"
+
+namespace hn {
+namespace {
+
+constexpr double kU32 = 1.0 / 8388608.0;               // 2^-23 (covers RNE and truncation)
+constexpr double kU64 = 1.0 / 9007199254740992.0;      // 2^-53
+constexpr double kUbf16 = 1.0 / 256.0;                 // 2^-8, bf16 round-to-nearest
+constexpr int kIdxNone = 0x7fffffff;
+
+// ---------------------------------------------------------------- queries
+
+struct QNorm {
+    double major, minor, full;  // rounded-up float64 block norms
+    double res16;               // ||bf16(q[:k]) - q[:k]||, rounded up
+    int bad;                    // non-finite component
+    int pad_;
+};
+
+__device__ __forceinline__ float bf16_rne(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+// One thread per (padded) query: norms and the float32 / bf16 operands.
+__global__ __launch_bounds__(256) void prep_queries(const float *__restrict__ q, int64_t nq,
+                                                    int64_t q_pad, int k, int w32, int w16,
+                                                    float *__restrict__ op32,
+                                                    uint16_t *__restrict__ op16,
+                                                    QNorm *__restrict__ qn) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= q_pad) return;
+    if (i >= nq) {
+        if (op32)
+            for (int c = 0; c < w32; ++c) op32[i * w32 + c] = 0.0f;
+        if (op16)
+            for (int c = 0; c < w16; ++c) op16[i * w16 + c] = 0;
+        return;
+    }
+    const float *v = q + i * kDim;
+    double sM = 0, sm = 0, sr = 0;
+    bool finite = true;
+    for (int j = 0; j < kDim; ++j) {
+        float f = v[j];
+        finite = finite && isfinite(f);
+        double d = (double)f;
+        if (j < k) {
+            sM = fma(d, d, sM);
+            double b = (double)bf16_rne(f);
+            sr = fma(b - d, b - d, sr);
+        } else {
+            sm = fma(d, d, sm);
+        }
+    }
+    const double up = 1.0 + ldexp(1.0, -40);
+    QNorm r;
+    r.major = sqrt(sM) * up;
+    r.minor = sqrt(sm) * up;
+    r.full = sqrt(sM + sm) * up;
+    r.res16 = sqrt(sr) * up;
+    r.bad = finite ? 0 : 1;
+    r.pad_ = 0;
+    qn[i] = r;
+    if (op32)
+        for (int c = 0; c < w32; ++c) op32[i * w32 + c] = (c < k && finite) ? v[c] : 0.0f;
+    if (op16)
+        for (int c = 0; c < w16; ++c)
+            op16[i * w16 + c] =
+                (c < k && finite) ? (uint16_t)(__float_as_uint(bf16_rne(v[c])) >> 16) : 0;
+}
+
+// ---------------------------------------------------------------- seed
+
+struct SeedArgs {
+    const float *part_val;
+    const int32_t *part_idx;
+    int32_t n_chunks, q_pad;
+    const float *queries;
+    int64_t q;
+    const float *rows;
+    int64_t n;
+    int32_t k;
+    double alpha, beta;  // beta = alpha for exact search
+    double mu_major, mu_minor, mu_full;
+    // scan slack: eps_scan = min(rel_a * major * mu_a, rel_b * major * mu_b +
+    //                            res_q_coef * res16 + res_x * major) + abs
+    double scan_rel, scan_mu, scan_abs;
+    int scan_res;  // use the residual-norm form as a second rigorous bound
+    double res_mu, res_x, res_acc_rel, res_acc_mu;
+    const double *lower;  // given L (filter-only); NULL: plain seed
+    const QNorm *qn;
+    float *thr;           // [q_pad]: scan threshold T_q (+inf for padding)
+    float *thr32;         // [q]: float32 re-check threshold, or NULL
+    int64_t *seed_idx;
+    double *seed_sim;
+    double *slack;
+    unsigned long long *best_key;
+    int32_t *best_idx;
+    int32_t *cnt;
+    int32_t *qflag;
+    unsigned long long *counter;
+};
+
+__device__ __forceinline__ float round_down_f32(double v) { return __double2float_rd(v); }
+
+__global__ __launch_bounds__(256) void seed_kernel(SeedArgs S) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) *S.counter = 0;
+    if (i >= S.q_pad) return;
+    if (i >= S.q) {
+        S.thr[i] = INFINITY;
+        return;
+    }
+    const QNorm qn = S.qn[i];
+    S.best_idx[i] = kIdxNone;
+    S.cnt[i] = 0;
+    S.qflag[i] = 0;
+    if (qn.bad) {
+        S.thr[i] = INFINITY;
+        if (S.thr32) S.thr32[i] = INFINITY;
+        S.seed_idx[i] = -1;
+        S.seed_sim[i] = NAN;
+        S.slack[i] = NAN;
+        S.best_key[i] = 0;
+        return;
+    }
+    const float *qv = S.queries + i * kDim;
+    double L;
+    int64_t b = -1;
+    if (S.lower) {
+        L = S.lower[i];
+    } else {
+        float bv = -INFINITY;
+        int bi = -1;
+        for (int c = 0; c < S.n_chunks; ++c)
+            lex_merge(bv, bi, S.part_val[(int64_t)c * S.q_pad + i],
+                      S.part_idx[(int64_t)c * S.q_pad + i]);
+        // rescore the winning 4-entry group; its best sim is the seed bound
+        L = -INFINITY;
+        for (int e = bi; e >= 0 && e < bi + 4 && e < S.n; ++e) {
+            double s = sim64(qv, S.rows + (int64_t)e * kDim);
+            if (b < 0 || s > L) {
+                L = s;
+                b = e;
+            }
+        }
+    }
+    // slack: scan rounding + stored-norm excess (Eq. 3) + float64 evaluation
+    double es = S.scan_rel * qn.major * S.scan_mu;
+    if (S.scan_res) {
+        double er = qn.res16 * S.res_mu + qn.major * S.res_x +
+                    S.res_acc_rel * (qn.major + qn.res16) * S.res_acc_mu;
+        es = fmin(es, er);
+    }
+    es += S.scan_abs;
+    double en = fmax(0.0, qn.minor * S.mu_minor - S.alpha);
+    double e64 = gamma_n(kDim, kU64) * qn.full * S.mu_full;
+    double eps = (es + en + e64) * (1.0 + ldexp(1.0, -30)) + ldexp(1.0, -40);
+    S.thr[i] = round_down_f32(L - S.beta - eps);
+    if (S.thr32) {
+        double e32 = gamma_n(S.k, kU32) * qn.major * S.mu_major + S.k * ldexp(1.0, -125);
+        double eps32 = (e32 + en + e64) * (1.0 + ldexp(1.0, -30)) + ldexp(1.0, -40);
+        S.thr32[i] = round_down_f32(L - S.beta - eps32);
+    }
+    S.seed_idx[i] = b;
+    S.seed_sim[i] = L;
+    S.slack[i] = eps;
+    S.best_key[i] = b >= 0 ? key_of(L) : 0ull;
+}
+
+// ------------------------------------------------------ rescoring & argmax
+
+struct RescoreArgs {
+    const int2 *pairs;
+    const float *pair_val;     // window mode: scan score of the pair
+    const unsigned long long *counter;
+    int64_t cap;
+    const float *queries, *rows;
+    const float *major32;      // re-check stream (low-precision scans)
+    int32_t kp, k;
+    const float *thr32;        // re-check / window threshold per query
+    double *psim;              // [cap]
+    unsigned long long *best_key;
+    int32_t *best_idx;
+    int32_t *cnt;
+    const int64_t *seed_idx;
+    const double *seed_sim;
+    int64_t q;
+};
+
+__device__ __forceinline__ int64_t pair_count(const RescoreArgs &R) {
+    unsigned long long c = *R.counter;
+    return (int64_t)c < R.cap ? (int64_t)c : R.cap;
+}
+
+// MODE 0: plain; 1: float32 re-check against thr32 first; 2: window re-filter.
+template <int MODE>
+__global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs R) {
+    const int64_t m = pair_count(R);
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < m;
+         p += (int64_t)gridDim.x * 256) {
+        const int2 pr = R.pairs[p];
+        const float *qv = R.queries + (int64_t)pr.x * kDim;
+        atomicAdd(&R.cnt[pr.x], 1);
+        bool keep = true;
+        if (MODE == 1) {
+            const float *xm = R.major32 + (int64_t)pr.y * R.kp;
+            float s = 0.0f;
+            for (int j = 0; j < R.k; ++j) s = fmaf(qv[j], xm[j], s);
+            keep = s >= R.thr32[pr.x];
+        } else if (MODE == 2) {
+            keep = R.pair_val[p] >= R.thr32[pr.x];
+        }
+        double s = -INFINITY;
+        if (keep) {
+            s = sim64(qv, R.rows + (int64_t)pr.y * kDim);
+            atomicMax(&R.best_key[pr.x], key_of(s));
+        }
+        R.psim[p] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void tie_kernel(RescoreArgs R) {
+    const int64_t m = pair_count(R);
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < m + R.q;
+         p += (int64_t)gridDim.x * 256) {
+        if (p < m) {
+            const double s = R.psim[p];
+            if (s == -INFINITY) continue;
+            const int2 pr = R.pairs[p];
+            if (key_of(s) == R.best_key[pr.x]) atomicMin(&R.best_idx[pr.x], pr.y);
+        } else if (R.seed_idx) {
+            const int64_t qi = p - m;
+            const int64_t b = R.seed_idx[qi];
+            if (b >= 0 && key_of(R.seed_sim[qi]) == R.best_key[qi])
+                atomicMin(&R.best_idx[qi], (int32_t)b);
+        }
+    }
+}
+
+// Exact completion of queries whose survivors did not fit the pair list: one
+// work-group per flagged query scans every entry.  full = 1 evaluates every
+// entry (exhaustive baseline); otherwise the float64 major score with the
+// rigorous float64 slack decides which entries get the full sim.
+struct FallbackArgs {
+    const int32_t *qflag;
+    const QNorm *qn;
+    const float *queries, *rows;
+    int64_t q, n;
+    int32_t k, full;
+    double beta, alpha, mu_major, mu_minor, mu_full;
+    const double *seed_sim;
+    unsigned long long *best_key;
+    int32_t *best_idx;
+    int32_t *cnt;
+};
+
+__global__ __launch_bounds__(256) void fallback_kernel(FallbackArgs F) {
+    __shared__ unsigned long long sk[256];
+    __shared__ int si[256];
+    __shared__ int sc[256];
+    for (int64_t qi = blockIdx.x; qi < F.q; qi += gridDim.x) {
+        if (!F.qflag[qi]) continue;
+        const float *qv = F.queries + qi * kDim;
+        const QNorm qn = F.qn[qi];
+        double lim = -INFINITY;
+        if (!F.full) {
+            double en = fmax(0.0, qn.minor * F.mu_minor - F.alpha);
+            double e = gamma_n(F.k, kU64) * qn.major * F.mu_major + en +
+                       gamma_n(kDim, kU64) * qn.full * F.mu_full;
+            lim = F.seed_sim[qi] - F.beta - e * (1.0 + ldexp(1.0, -30)) - ldexp(1.0, -40);
+        }
+        unsigned long long bk = 0;
+        int bi = kIdxNone, c = 0;
+        for (int64_t e = threadIdx.x; e < F.n; e += 256) {
+            const float *xv = F.rows + e * kDim;
+            if (!F.full) {
+                double s = 0.0;
+                for (int j = 0; j < F.k; ++j) s = fma((double)qv[j], (double)xv[j], s);
+                if (s < lim) continue;
+            }
+            ++c;
+            unsigned long long kk = key_of(sim64(qv, xv));
+            if (kk > bk || (kk == bk && (int)e < bi)) {
+                bk = kk;
+                bi = (int)e;
+            }
+        }
+        sk[threadIdx.x] = bk;
+        si[threadIdx.x] = bi;
+        sc[threadIdx.x] = c;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) {
+                unsigned long long ok = sk[threadIdx.x + o];
+                int oi = si[threadIdx.x + o];
+                if (ok > sk[threadIdx.x] || (ok == sk[threadIdx.x] && oi < si[threadIdx.x])) {
+                    sk[threadIdx.x] = ok;
+                    si[threadIdx.x] = oi;
+                }
+                sc[threadIdx.x] += sc[threadIdx.x + o];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            F.best_key[qi] = sk[0];
+            F.best_idx[qi] = si[0];
+            F.cnt[qi] = sc[0];
+        }
+        __syncthreads();
+    }
+}
+
+struct FinalArgs {
+    int64_t q;
+    const QNorm *qn;
+    const unsigned long long *best_key;
+    const int32_t *best_idx;
+    const int32_t *cnt;
+    const int32_t *qflag;
+    int64_t *out_idx;
+    double *out_sim;
+    hn_search_aux aux;
+    const int64_t *seed_idx;
+    const double *seed_sim;
+    const float *thr;
+    const double *slack;
+    unsigned long long *n_flagged;
+};
+
+__global__ __launch_bounds__(256) void finalize_kernel(FinalArgs F) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= F.q) return;
+    const bool bad = F.qn[i].bad != 0;
+    F.out_idx[i] = bad ? -1 : (int64_t)F.best_idx[i];
+    F.out_sim[i] = bad ? (double)NAN : sim_of_key(F.best_key[i]);
+    if (F.aux.survivors) F.aux.survivors[i] = F.cnt[i];
+    if (F.aux.seed_idx) F.aux.seed_idx[i] = F.seed_idx ? F.seed_idx[i] : -1;
+    if (F.aux.seed_sim) F.aux.seed_sim[i] = F.seed_sim ? F.seed_sim[i] : (double)NAN;
+    if (F.aux.threshold) F.aux.threshold[i] = F.thr ? F.thr[i] : (float)NAN;
+    if (F.aux.slack) F.aux.slack[i] = F.slack ? F.slack[i] : (double)NAN;
+    if (F.n_flagged && F.qflag[i]) atomicAdd(F.n_flagged, 1ull);
+}
+
+// ------------------------------------------------- brute-force helpers
+
+__global__ __launch_bounds__(256) void bf_db_norm(const float *__restrict__ db, int64_t n,
+                                                  unsigned long long *mu_key) {
+    __shared__ double sh[4];
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double v = 0.0;
+    if (i < n) {
+        const float *x = db + i * kDim;
+        double s = 0.0;
+        for (int j = 0; j < kDim; ++j) s = fma((double)x[j], (double)x[j], s);
+        v = sqrt(s);
+    }
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(mu_key, key_of(fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]))));
+}
+
+__global__ void zero_u64(unsigned long long *p, int count) {
+    if ((int)threadIdx.x < count) p[threadIdx.x] = 0ull;
+}
+
+// Window width for the exhaustive float32 scan: the true argmax has s~ no
+// lower than the scan maximum minus 2 (eps_f32 + eps_f64).
+struct BfPrepArgs {
+    const QNorm *qn;
+    const unsigned long long *mu_key;
+    int64_t q, q_pad;
+    float *win_scan;  // widened for the float32 subtraction in the scan
+    double *win;      // exact window for the re-filter
+    unsigned long long *best_key;
+    int32_t *best_idx, *cnt, *qflag;
+    unsigned long long *counter;
+};
+
+__global__ __launch_bounds__(256) void bf_prep(BfPrepArgs P) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) *P.counter = 0;
+    if (i >= P.q_pad) return;
+    if (i >= P.q) {
+        P.win_scan[i] = 0.0f;
+        return;
+    }
+    const double mu = sim_of_key(*P.mu_key) * (1.0 + ldexp(1.0, -40));
+    const QNorm qn = P.qn[i];
+    const double scale = qn.full * mu;
+    double w = 2.0 * (gamma_n(kDim, kU32) * scale + kDim * ldexp(1.0, -125) +
+                      gamma_n(kDim, kU64) * scale);
+    w = w * (1.0 + ldexp(1.0, -20)) + ldexp(1.0, -100);
+    P.win[i] = w;
+    P.win_scan[i] = __double2float_ru(w + ldexp(1.0, -22) * scale);
+    P.best_key[i] = 0ull;
+    P.best_idx[i] = kIdxNone;
+    P.cnt[i] = 0;
+    P.qflag[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void bf_threshold(const float *part_val, int32_t n_chunks,
+                                                    int32_t q_pad, int64_t q, const double *win,
+                                                    float *thr) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= q) return;
+    float m = -INFINITY;
+    for (int c = 0; c < n_chunks; ++c) m = fmaxf(m, part_val[(int64_t)c * q_pad + i]);
+    thr[i] = __double2float_rd((double)m - win[i]);
+}
+
+// ---------------------------------------------------------- launch helpers
+
+unsigned blocks_for(int64_t items, int per = 256) {
+    return (unsigned)std::max<int64_t>(1, (items + per - 1) / per);
+}
+
+struct Plan {
+    int nq = 4, wq = 4;  // 16-query tiles per wave, query sub-blocks per group
+    int qb_size() const { return nq * wq * 16; }
+    int32_t n_qb = 0, chunk_blocks = 0, n_chunks = 0, n_items = 0;
+    int64_t q_pad = 0;
+    unsigned grid = 0;
+};
+
+// Configurations compiled for each operand policy: (NQ, WQ).
+constexpr int kNumCfg = 6;
+constexpr int kCfgNQ[kNumCfg] = {1, 2, 4, 2, 4, 8};
+constexpr int kCfgWQ[kNumCfg] = {1, 1, 1, 4, 4, 4};
+
+int pick_cfg(int64_t q, int slice_regs, int forced_nq) {
+    int best = 0;
+    for (int c = 0; c < kNumCfg; ++c) {
+        if (kCfgNQ[c] * slice_regs > 64) continue;
+        if (forced_nq > 0 && kCfgNQ[c] != forced_nq) continue;
+        best = c;
+        if ((int64_t)kCfgNQ[c] * kCfgWQ[c] * 16 >= q) break;
+    }
+    return best;
+}
+
+Plan make_plan(int64_t n, int64_t q, int cfg, int chunk_blocks) {
+    Plan p;
+    p.nq = kCfgNQ[cfg];
+    p.wq = kCfgWQ[cfg];
+    const int64_t qb = p.qb_size();
+    p.n_qb = (int32_t)((q + qb - 1) / qb);
+    p.q_pad = (int64_t)p.n_qb * qb;
+    const int32_t n_blocks = (int32_t)((n + 15) / 16);
+    if (chunk_blocks <= 0) {
+        const int64_t target_items = 2048;
+        int64_t want_chunks = std::max<int64_t>(1, (target_items + p.n_qb - 1) / p.n_qb);
+        chunk_blocks = (int32_t)std::max<int64_t>(8, (n_blocks + want_chunks - 1) / want_chunks);
+    }
+    p.chunk_blocks = std::min<int32_t>(chunk_blocks, n_blocks);
+    p.n_chunks = (n_blocks + p.chunk_blocks - 1) / p.chunk_blocks;
+    p.n_items = p.n_qb * p.n_chunks;
+    p.grid = (unsigned)((p.n_items + kXcds - 1) / kXcds * kXcds);
+    return p;
+}
+
+template <class Tile, int MODE>
+void launch_scan_cfg(int cfg, const Plan &p, const ScanArgs &A, hipStream_t s) {
+    switch (cfg) {
+#define HN_CFG(c)                                                                      \
+    case c:                                                                            \
+        if constexpr (kCfgNQ[c] * Tile::kSlice * sizeof(typename Tile::Elem) / 4 <= 64) \
+            hipLaunchKernelGGL((scan_kernel<Tile, kCfgNQ[c], kCfgWQ[c], MODE>), dim3(p.grid), \
+                               dim3(256), 0, s, A);                                    \
+        break;
+        HN_CFG(0)
+        HN_CFG(1)
+        HN_CFG(2)
+        HN_CFG(3)
+        HN_CFG(4)
+        HN_CFG(5)
+#undef HN_CFG
+    }
+}
+
+// precision 0: float32 stream of width w; 1: bf16 stream of width w.
+const char *scan_tag(int mode, int precision) {
+    static const char *const tags[4][2] = {
+        {"scan_argmax_f32", "scan_argmax_bf16"},
+        {"scan_filter_f32", "scan_filter_bf16"},
+        {"scan_window_f32", "scan_window_bf16"},
+        {"scan_store_f32", "scan_store_bf16"}};
+    return tags[mode][precision == HN_PREC_FP32 ? 0 : 1];
+}
+
+template <int MODE>
+int launch_scan(int precision, int w, int cfg, const Plan &p, const ScanArgs &A,
+                hipStream_t s) {
+    ProfScope prof(s, scan_tag(MODE, precision));
+    if (precision == HN_PREC_FP32) {
+        switch (w) {
+            case 4: launch_scan_cfg<F32Tile<4>, MODE>(cfg, p, A, s); break;
+            case 8: launch_scan_cfg<F32Tile<8>, MODE>(cfg, p, A, s); break;
+            case 16: launch_scan_cfg<F32Tile<16>, MODE>(cfg, p, A, s); break;
+            case 32: launch_scan_cfg<F32Tile<32>, MODE>(cfg, p, A, s); break;
+            case 64: launch_scan_cfg<F32Tile<64>, MODE>(cfg, p, A, s); break;
+            case 128: launch_scan_cfg<F32Tile<128>, MODE>(cfg, p, A, s); break;
+            default: return fail(HN_ERR_INVALID_ARG, "bad stream width %d", w);
+        }
+    } else if (precision == HN_PREC_BF16) {
+        switch (w) {
+            case 16: launch_scan_cfg<BF16Tile<16>, MODE>(cfg, p, A, s); break;
+            case 32: launch_scan_cfg<BF16Tile<32>, MODE>(cfg, p, A, s); break;
+            case 64: launch_scan_cfg<BF16Tile<64>, MODE>(cfg, p, A, s); break;
+            case 128: launch_scan_cfg<BF16Tile<128>, MODE>(cfg, p, A, s); break;
+            default: return fail(HN_ERR_INVALID_ARG, "bad stream width %d", w);
+        }
+    } else {
+        return fail(HN_ERR_UNSUPPORTED, "precision %d is not available", precision);
+    }
+    HN_HIP(hipGetLastError());
+    return HN_OK;
+}
+
+int slice_regs(int precision, int w) { return precision == HN_PREC_FP32 ? w / 4 : w / 8; }
+
+// Everything one search call needs on the device.
+struct Work {
+    Plan plan;
+    int cfg = 0;
+    int precision = HN_PREC_FP32;
+    int width = 0;
+    const void *stream_x = nullptr;
+    float *op32 = nullptr;
+    uint16_t *op16 = nullptr;
+    QNorm *qn = nullptr;
+    float *part_val = nullptr;
+    int32_t *part_idx = nullptr;
+    float *thr = nullptr, *thr32 = nullptr;
+    int64_t *seed_idx = nullptr;
+    double *seed_sim = nullptr, *slack = nullptr;
+    unsigned long long *best_key = nullptr, *counter = nullptr, *n_flagged = nullptr;
+    int32_t *best_idx = nullptr, *cnt = nullptr, *qflag = nullptr;
+    int2 *pairs = nullptr;
+    double *psim = nullptr;
+    int64_t cap = 0;
+};
+
+int validate_opts(const hn_index *ix, const hn_search_opts *o) {
+    if (!o) return HN_OK;
+    if (o->precision != HN_PREC_FP32 && o->precision != HN_PREC_BF16)
+        return fail(HN_ERR_UNSUPPORTED, "precision %d is not available", o->precision);
+    if (o->seed != HN_SEED_PLAIN) return fail(HN_ERR_UNSUPPORTED, "seed %d is not available", o->seed);
+    if (o->query_tiles != 0 && o->query_tiles != 1 && o->query_tiles != 2 && o->query_tiles != 4 &&
+        o->query_tiles != 8)
+        return fail(HN_ERR_INVALID_ARG, "query_tiles must be 0, 1, 2, 4 or 8");
+    if (o->chunk_blocks < 0) return fail(HN_ERR_INVALID_ARG, "chunk_blocks must be >= 0");
+    if (o->survivor_cap < 0) return fail(HN_ERR_INVALID_ARG, "survivor_cap must be >= 0");
+    if (!(o->beta < 0.0 || (o->beta >= 0.0 && o->beta <= ix->alpha)))
+        return fail(HN_ERR_INVALID_ARG, "beta must be < 0 (exact) or in [0, alpha]");
+    return HN_OK;
+}
+
+// Prepare queries, run the plain-seed pass and compute thresholds.  With
+// `lower` the seed pass is skipped and L is taken from the caller.
+int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_search_opts &o,
+               const double *lower, int64_t cap, Work &W, hipStream_t s) {
+    W.precision = o.precision;
+    W.width = W.precision == HN_PREC_FP32 ? ix->kp : ix->kb;
+    W.stream_x = W.precision == HN_PREC_FP32 ? (const void *)ix->major32 : (const void *)ix->major16;
+    W.cfg = pick_cfg(q, slice_regs(W.precision, W.width), o.query_tiles);
+    W.plan = make_plan(ix->n, q, W.cfg, o.chunk_blocks);
+    const Plan &p = W.plan;
+    W.cap = cap;
+
+    size_t bytes = 0;
+    auto add = [&](size_t count, size_t sz) { bytes += (count * sz + 255) & ~size_t(255); };
+    add(p.q_pad * ix->kp, 4);
+    add(p.q_pad * ix->kb, 2);
+    add(p.q_pad, sizeof(QNorm));
+    add((size_t)p.n_chunks * p.q_pad, 4);
+    add((size_t)p.n_chunks * p.q_pad, 4);
+    add(p.q_pad, 4);
+    add(q, 4);
+    add(q, 8);
+    add(q, 8);
+    add(q, 8);
+    add(q, 8);
+    add(q, 4);
+    add(q, 4);
+    add(q, 4);
+    add(4, 8);
+    add(cap, sizeof(int2));
+    add(cap, 8);
+    Arena *ar = nullptr;
+    int rc = arena_for((void *)s, bytes, &ar);
+    if (rc) return rc;
+    W.op32 = ar->take<float>(p.q_pad * ix->kp);
+    W.op16 = ar->take<uint16_t>(p.q_pad * ix->kb);
+    W.qn = ar->take<QNorm>(p.q_pad);
+    W.part_val = ar->take<float>((size_t)p.n_chunks * p.q_pad);
+    W.part_idx = ar->take<int32_t>((size_t)p.n_chunks * p.q_pad);
+    W.thr = ar->take<float>(p.q_pad);
+    W.thr32 = ar->take<float>(q);
+    W.seed_idx = ar->take<int64_t>(q);
+    W.seed_sim = ar->take<double>(q);
+    W.slack = ar->take<double>(q);
+    W.best_key = ar->take<unsigned long long>(q);
+    W.best_idx = ar->take<int32_t>(q);
+    W.cnt = ar->take<int32_t>(q);
+    W.qflag = ar->take<int32_t>(q);
+    W.counter = ar->take<unsigned long long>(4);
+    W.n_flagged = W.counter + 1;
+    W.pairs = ar->take<int2>(cap);
+    W.psim = ar->take<double>(cap);
+
+    {
+        ProfScope prof_(s, "prep_queries");
+        hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, queries, q,
+                           p.q_pad, ix->k, ix->kp, ix->kb, W.op32, W.op16, W.qn);
+    }
+    HN_HIP(hipGetLastError());
+
+    ScanArgs A;
+    memset(&A, 0, sizeof A);
+    A.x = W.stream_x;
+    A.x_stride = W.width;
+    A.qs = W.precision == HN_PREC_FP32 ? (const void *)W.op32 : (const void *)W.op16;
+    A.q_stride = W.width;
+    A.n = ix->n;
+    A.n_blocks = (int32_t)((ix->n + 15) / 16);
+    A.chunk_blocks = p.chunk_blocks;
+    A.n_chunks = p.n_chunks;
+    A.n_qb = p.n_qb;
+    A.n_items = p.n_items;
+    A.q_count = (int32_t)q;
+    A.q_pad = (int32_t)p.q_pad;
+    A.part_val = W.part_val;
+    A.part_idx = W.part_idx;
+    if (!lower) {
+        rc = launch_scan<kArgmax>(W.precision, W.width, W.cfg, p, A, s);
+        if (rc) return rc;
+    }
+
+    SeedArgs S;
+    memset(&S, 0, sizeof S);
+    S.part_val = W.part_val;
+    S.part_idx = W.part_idx;
+    S.n_chunks = p.n_chunks;
+    S.q_pad = (int32_t)p.q_pad;
+    S.queries = queries;
+    S.q = q;
+    S.rows = ix->rows;
+    S.n = ix->n;
+    S.k = ix->k;
+    S.alpha = ix->alpha;
+    S.beta = o.beta < 0.0 ? ix->alpha : o.beta;
+    S.mu_major = ix->mu_major;
+    S.mu_minor = ix->mu_minor;
+    S.mu_full = ix->mu_full;
+    if (W.precision == HN_PREC_FP32) {
+        S.scan_rel = gamma_n(ix->k, kU32);
+        S.scan_mu = ix->mu_major;
+        S.scan_abs = ix->k * ldexp(1.0, -125);
+        S.scan_res = 0;
+    } else {
+        // worst case: both roundings relative 2^-8, then float32 accumulation
+        const double ub = kUbf16;
+        S.scan_rel = (2 * ub + ub * ub) + gamma_n(ix->k, kU32) * (1 + ub) * (1 + ub);
+        S.scan_mu = ix->mu_major;
+        S.scan_abs = ix->k * ldexp(1.0, -125);
+        // residual form (Cauchy-Schwarz on the rounding residuals):
+        // |sum(q^x^ - qx)| <= ||q^-q|| ||x^|| + ||q|| ||x^-x||, plus accumulation
+        S.scan_res = 1;
+        S.res_mu = ix->mu_major16;
+        S.res_x = ix->res16;
+        S.res_acc_rel = gamma_n(ix->k, kU32);
+        S.res_acc_mu = ix->mu_major16;
+    }
+    S.lower = lower;
+    S.qn = W.qn;
+    S.thr = W.thr;
+    S.thr32 = W.precision == HN_PREC_FP32 ? nullptr : W.thr32;
+    S.seed_idx = W.seed_idx;
+    S.seed_sim = W.seed_sim;
+    S.slack = W.slack;
+    S.best_key = W.best_key;
+    S.best_idx = W.best_idx;
+    S.cnt = W.cnt;
+    S.qflag = W.qflag;
+    S.counter = W.counter;
+    {
+        ProfScope prof_(s, "seed");
+        hipLaunchKernelGGL(seed_kernel, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, S);
+    }
+    HN_HIP(hipGetLastError());
+    return HN_OK;
+}
+
+ScanArgs filter_args(const hn_index *ix, const Work &W, int64_t q, int2 *pairs, int64_t cap) {
+    const Plan &p = W.plan;
+    ScanArgs A;
+    memset(&A, 0, sizeof A);
+    A.x = W.stream_x;
+    A.x_stride = W.width;
+    A.qs = W.precision == HN_PREC_FP32 ? (const void *)W.op32 : (const void *)W.op16;
+    A.q_stride = W.width;
+    A.n = ix->n;
+    A.n_blocks = (int32_t)((ix->n + 15) / 16);
+    A.chunk_blocks = p.chunk_blocks;
+    A.n_chunks = p.n_chunks;
+    A.n_qb = p.n_qb;
+    A.n_items = p.n_items;
+    A.q_count = (int32_t)q;
+    A.q_pad = (int32_t)p.q_pad;
+    A.thr = W.thr;
+    A.pairs = pairs;
+    A.counter = W.counter;
+    A.cap = cap;
+    A.qflag = W.qflag;
+    return A;
+}
+
+int64_t default_cap(int64_t n, int64_t q) {
+    int64_t per = std::max<int64_t>(2048, n / 512);
+    int64_t c = q * per;
+    return std::min<int64_t>(std::max<int64_t>(c, (int64_t)1 << 20), (int64_t)1 << 28);
+}
+
+}  // namespace
+}  // namespace hn
+
+using namespace hn;
+
+extern "C" int hn_search_top1(const hn_index *ix, const float *queries, int64_t q,
+                              int64_t *out_idx, double *out_sim, const hn_search_opts *opts,
+                              const hn_search_aux *aux, hn_search_stats *stats, void *stream) {
+    clear_error();
+    if (!ix) return fail(HN_ERR_INVALID_ARG, "null index");
+    if (q < 0) return fail(HN_ERR_INVALID_ARG, "q must be >= 0");
+    if (q >= ((int64_t)1 << 31) - 4096) return fail(HN_ERR_UNSUPPORTED, "q must be < 2^31");
+    if (q > 0 && (!queries || !out_idx || !out_sim))
+        return fail(HN_ERR_INVALID_ARG, "null queries or outputs");
+    int rc = validate_opts(ix, opts);
+    if (rc) return rc;
+    if (stats) memset(stats, 0, sizeof *stats);
+    if (q == 0) return HN_OK;
+    hn_search_opts o = opts ? *opts : hn_search_opts{HN_PREC_FP32, HN_SEED_PLAIN, 0, 0, 0, -1.0};
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t cap = o.survivor_cap > 0 ? o.survivor_cap : default_cap(ix->n, q);
+
+    Work W;
+    rc = stage_seed(ix, queries, q, o, nullptr, cap, W, s);
+    if (rc) return rc;
+    ScanArgs A = filter_args(ix, W, q, W.pairs, cap);
+    rc = launch_scan<kFilter>(W.precision, W.width, W.cfg, W.plan, A, s);
+    if (rc) return rc;
+
+    RescoreArgs R;
+    memset(&R, 0, sizeof R);
+    R.pairs = W.pairs;
+    R.counter = W.counter;
+    R.cap = cap;
+    R.queries = queries;
+    R.rows = ix->rows;
+    R.major32 = ix->major32;
+    R.kp = ix->kp;
+    R.k = ix->k;
+    R.thr32 = W.thr32;
+    R.psim = W.psim;
+    R.best_key = W.best_key;
+    R.best_idx = W.best_idx;
+    R.cnt = W.cnt;
+    R.seed_idx = W.seed_idx;
+    R.seed_sim = W.seed_sim;
+    R.q = q;
+    const unsigned rgrid = 2048;
+    if (W.precision == HN_PREC_FP32) {
+        ProfScope prof_(s, "rescore");
+        hipLaunchKernelGGL(rescore_kernel<0>, dim3(rgrid), dim3(256), 0, s, R);
+    } else {
+        ProfScope prof_(s, "rescore_recheck");
+        hipLaunchKernelGGL(rescore_kernel<1>, dim3(rgrid), dim3(256), 0, s, R);
+    }
+    {
+        ProfScope prof_(s, "tie");
+        hipLaunchKernelGGL(tie_kernel, dim3(rgrid), dim3(256), 0, s, R);
+    }
+
+    FallbackArgs F;
+    memset(&F, 0, sizeof F);
+    F.qflag = W.qflag;
+    F.qn = W.qn;
+    F.queries = queries;
+    F.rows = ix->rows;
+    F.q = q;
+    F.n = ix->n;
+    F.k = ix->k;
+    F.full = 0;
+    F.beta = o.beta < 0.0 ? ix->alpha : o.beta;
+    F.alpha = ix->alpha;
+    F.mu_major = ix->mu_major;
+    F.mu_minor = ix->mu_minor;
+    F.mu_full = ix->mu_full;
+    F.seed_sim = W.seed_sim;
+    F.best_key = W.best_key;
+    F.best_idx = W.best_idx;
+    F.cnt = W.cnt;
+    {
+        ProfScope prof_(s, "fallback");
+        hipLaunchKernelGGL(fallback_kernel, dim3((unsigned)std::min<int64_t>(q, 1024)), dim3(256), 0,
+                           s, F);
+    }
+
+    FinalArgs Z;
+    memset(&Z, 0, sizeof Z);
+    Z.q = q;
+    Z.qn = W.qn;
+    Z.best_key = W.best_key;
+    Z.best_idx = W.best_idx;
+    Z.cnt = W.cnt;
+    Z.qflag = W.qflag;
+    Z.out_idx = out_idx;
+    Z.out_sim = out_sim;
+    if (aux) Z.aux = *aux;
+    Z.seed_idx = W.seed_idx;
+    Z.seed_sim = W.seed_sim;
+    Z.thr = W.thr;
+    Z.slack = W.slack;
+    Z.n_flagged = stats ? W.n_flagged : nullptr;
+    if (stats) hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, s, W.n_flagged, 1);
+    {
+        ProfScope prof_(s, "finalize");
+        hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(q)), dim3(256), 0, s, Z);
+    }
+    HN_HIP(hipGetLastError());
+    if (stats) {
+        unsigned long long h[2];
+        HN_HIP(hipMemcpyAsync(h, W.counter, sizeof h, hipMemcpyDeviceToHost, s));
+        HN_HIP(hipStreamSynchronize(s));
+        stats->survivors = (int64_t)h[0];
+        stats->overflow_queries = (int64_t)h[1];
+    }
+    return HN_OK;
+}
+
+extern "C" int hn_filter_survivors(const hn_index *ix, const float *queries, int64_t q,
+                                   const double *lower, int32_t *pairs, int64_t cap,
+                                   int64_t *count, double *slack, const hn_search_opts *opts,
+                                   void *stream) {
+    clear_error();
+    if (!ix) return fail(HN_ERR_INVALID_ARG, "null index");
+    if (q < 0 || cap < 0) return fail(HN_ERR_INVALID_ARG, "q and cap must be >= 0");
+    if (!count) return fail(HN_ERR_INVALID_ARG, "count is null");
+    if (q > 0 && (!queries || !lower || (cap > 0 && !pairs)))
+        return fail(HN_ERR_INVALID_ARG, "null queries, lower bounds or pairs");
+    int rc = validate_opts(ix, opts);
+    if (rc) return rc;
+    *count = 0;
+    if (q == 0) return HN_OK;
+    hn_search_opts o = opts ? *opts : hn_search_opts{HN_PREC_FP32, HN_SEED_PLAIN, 0, 0, 0, -1.0};
+    hipStream_t s = (hipStream_t)stream;
+    Work W;
+    rc = stage_seed(ix, queries, q, o, lower, 1, W, s);
+    if (rc) return rc;
+    ScanArgs A = filter_args(ix, W, q, reinterpret_cast<int2 *>(pairs), cap);
+    rc = launch_scan<kFilter>(W.precision, W.width, W.cfg, W.plan, A, s);
+    if (rc) return rc;
+    if (slack) HN_HIP(hipMemcpyAsync(slack, W.slack, q * sizeof(double), hipMemcpyDeviceToDevice, s));
+    unsigned long long h = 0;
+    HN_HIP(hipMemcpyAsync(&h, W.counter, sizeof h, hipMemcpyDeviceToHost, s));
+    HN_HIP(hipStreamSynchronize(s));
+    *count = (int64_t)h;
+    return HN_OK;
+}
+
+extern "C" int hn_scan_scores(const hn_index *ix, const float *queries, int64_t q,
+                              int32_t precision, float *scores, void *stream) {
+    clear_error();
+    if (!ix) return fail(HN_ERR_INVALID_ARG, "null index");
+    if (q < 0) return fail(HN_ERR_INVALID_ARG, "q must be >= 0");
+    if (q > 0 && (!queries || !scores)) return fail(HN_ERR_INVALID_ARG, "null queries or scores");
+    if (precision != HN_PREC_FP32 && precision != HN_PREC_BF16)
+        return fail(HN_ERR_UNSUPPORTED, "precision %d is not available", precision);
+    if (q == 0) return HN_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hn_search_opts o{precision, HN_SEED_PLAIN, 0, 0, 0, -1.0};
+    Work W;
+    W.precision = precision;
+    W.width = precision == HN_PREC_FP32 ? ix->kp : ix->kb;
+    W.cfg = 0;
+    W.plan = make_plan(ix->n, q, W.cfg, 0);
+    (void)o;
+    const Plan &p = W.plan;
+    size_t bytes = ((p.q_pad * ix->kp * 4 + 255) & ~size_t(255)) +
+                   ((p.q_pad * ix->kb * 2 + 255) & ~size_t(255)) +
+                   ((p.q_pad * sizeof(QNorm) + 255) & ~size_t(255));
+    Arena *ar = nullptr;
+    int rc = arena_for(stream, bytes, &ar);
+    if (rc) return rc;
+    W.op32 = ar->take<float>(p.q_pad * ix->kp);
+    W.op16 = ar->take<uint16_t>(p.q_pad * ix->kb);
+    W.qn = ar->take<QNorm>(p.q_pad);
+    hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, queries, q,
+                       p.q_pad, ix->k, ix->kp, ix->kb, W.op32, W.op16, W.qn);
+    ScanArgs A;
+    memset(&A, 0, sizeof A);
+    A.x = precision == HN_PREC_FP32 ? (const void *)ix->major32 : (const void *)ix->major16;
+    A.x_stride = W.width;
+    A.qs = precision == HN_PREC_FP32 ? (const void *)W.op32 : (const void *)W.op16;
+    A.q_stride = W.width;
+    A.n = ix->n;
+    A.n_blocks = (int32_t)((ix->n + 15) / 16);
+    A.chunk_blocks = p.chunk_blocks;
+    A.n_chunks = p.n_chunks;
+    A.n_qb = p.n_qb;
+    A.n_items = p.n_items;
+    A.q_count = (int32_t)q;
+    A.q_pad = (int32_t)p.q_pad;
+    A.scores = scores;
+    return launch_scan<kStore>(precision, W.width, W.cfg, p, A, s);
+}
+
+extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const float *queries,
+                                  int64_t q, int64_t *out_idx, double *out_sim, void *stream) {
+    clear_error();
+    if (d != kDim) return fail(HN_ERR_INVALID_ARG, "d must be 128 (got %d)", d);
+    if (n < 1) return fail(HN_ERR_INVALID_ARG, "n must be >= 1");
+    if (n >= (int64_t)1 << 31) return fail(HN_ERR_UNSUPPORTED, "n must be < 2^31");
+    if (q < 0) return fail(HN_ERR_INVALID_ARG, "q must be >= 0");
+    if (!db || (q > 0 && (!queries || !out_idx || !out_sim)))
+        return fail(HN_ERR_INVALID_ARG, "null pointer argument");
+    if (q == 0) return HN_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int cfg = pick_cfg(q, kDim / 4, 2);
+    Plan p = make_plan(n, q, cfg, 0);
+    const int64_t cap = std::min<int64_t>(std::max<int64_t>(q * 256, 1 << 16), (int64_t)1 << 26);
+
+    size_t bytes = 0;
+    auto add = [&](size_t count, size_t sz) { bytes += (count * sz + 255) & ~size_t(255); };
+    add(p.q_pad, sizeof(QNorm));
+    add((size_t)p.n_chunks * p.q_pad, 4);
+    add(p.q_pad, 4);
+    add(q, 8);
+    add(q, 4);
+    add(q, 8);
+    add(q, 4);
+    add(q, 4);
+    add(q, 4);
+    add(4, 8);
+    add(cap, sizeof(int2));
+    add(cap, 4);
+    add(cap, 8);
+    Arena *ar = nullptr;
+    int rc = arena_for(stream, bytes, &ar);
+    if (rc) return rc;
+    QNorm *qn = ar->take<QNorm>(p.q_pad);
+    float *part_val = ar->take<float>((size_t)p.n_chunks * p.q_pad);
+    float *win_scan = ar->take<float>(p.q_pad);
+    double *win = ar->take<double>(q);
+    float *thr = ar->take<float>(q);
+    unsigned long long *best_key = ar->take<unsigned long long>(q);
+    int32_t *best_idx = ar->take<int32_t>(q);
+    int32_t *cnt = ar->take<int32_t>(q);
+    int32_t *qflag = ar->take<int32_t>(q);
+    unsigned long long *counter = ar->take<unsigned long long>(4);
+    unsigned long long *mu_key = counter + 1;
+    int2 *pairs = ar->take<int2>(cap);
+    float *pair_val = ar->take<float>(cap);
+    double *psim = ar->take<double>(cap);
+
+    hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, s, counter, 4);
+    {
+        ProfScope prof_(s, "bf_db_norm");
+        hipLaunchKernelGGL(bf_db_norm, dim3(blocks_for(n)), dim3(256), 0, s, db, n, mu_key);
+    }
+    hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, queries, q,
+                       p.q_pad, kDim - 1, 0, 0, (float *)nullptr, (uint16_t *)nullptr, qn);
+    BfPrepArgs P{qn, mu_key, q, p.q_pad, win_scan, win, best_key, best_idx, cnt, qflag, counter};
+    {
+        ProfScope prof_(s, "bf_prep");
+        hipLaunchKernelGGL(bf_prep, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, P);
+    }
+
+    ScanArgs A;
+    memset(&A, 0, sizeof A);
+    A.x = db;
+    A.x_stride = kDim;
+    A.qs = queries;
+    A.q_stride = kDim;
+    A.n = n;
+    A.n_blocks = (int32_t)((n + 15) / 16);
+    A.chunk_blocks = p.chunk_blocks;
+    A.n_chunks = p.n_chunks;
+    A.n_qb = p.n_qb;
+    A.n_items = p.n_items;
+    A.q_count = (int32_t)q;
+    A.q_pad = (int32_t)p.q_pad;
+    A.part_val = part_val;
+    A.thr = win_scan;
+    A.pairs = pairs;
+    A.pair_val = pair_val;
+    A.counter = counter;
+    A.cap = cap;
+    A.qflag = qflag;
+    rc = launch_scan<kWindow>(HN_PREC_FP32, kDim, cfg, p, A, s);
+    if (rc) return rc;
+    {
+        ProfScope prof_(s, "bf_threshold");
+        hipLaunchKernelGGL(bf_threshold, dim3(blocks_for(q)), dim3(256), 0, s, part_val, p.n_chunks,
+                           (int32_t)p.q_pad, q, win, thr);
+    }
+
+    RescoreArgs R;
+    memset(&R, 0, sizeof R);
+    R.pairs = pairs;
+    R.pair_val = pair_val;
+    R.counter = counter;
+    R.cap = cap;
+    R.queries = queries;
+    R.rows = db;
+    R.thr32 = thr;
+    R.psim = psim;
+    R.best_key = best_key;
+    R.best_idx = best_idx;
+    R.cnt = cnt;
+    R.q = q;
+    {
+        ProfScope prof_(s, "bf_rescore");
+        hipLaunchKernelGGL(rescore_kernel<2>, dim3(1024), dim3(256), 0, s, R);
+    }
+    {
+        ProfScope prof_(s, "bf_tie");
+        hipLaunchKernelGGL(tie_kernel, dim3(1024), dim3(256), 0, s, R);
+    }
+
+    FallbackArgs F;
+    memset(&F, 0, sizeof F);
+    F.qflag = qflag;
+    F.qn = qn;
+    F.queries = queries;
+    F.rows = db;
+    F.q = q;
+    F.n = n;
+    F.k = kDim;
+    F.full = 1;
+    F.best_key = best_key;
+    F.best_idx = best_idx;
+    F.cnt = cnt;
+    hipLaunchKernelGGL(fallback_kernel, dim3((unsigned)std::min<int64_t>(q, 1024)), dim3(256), 0,
+                       s, F);
+
+    FinalArgs Z;
+    memset(&Z, 0, sizeof Z);
+    Z.q = q;
+    Z.qn = qn;
+    Z.best_key = best_key;
+    Z.best_idx = best_idx;
+    Z.cnt = cnt;
+    Z.qflag = qflag;
+    Z.out_idx = out_idx;
+    Z.out_sim = out_sim;
+    hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(q)), dim3(256), 0, s, Z);
+    HN_HIP(hipGetLastError());
+    return HN_OK;
+}

@@ -1,0 +1,333 @@
+"""GPU parity of the HIP path against the CPU float64 oracle, through the C ABI.
+
+Indices must be bit-exact and similarities equal to the oracle's canonical
+float64 sim (tolerance 1e-12; the kernels reproduce the canonical sum, so the
+expected difference is 0).  Survivor sets are checked against the oracle's
+exact seed-threshold sets S(q, L) with the GPU's own L.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import hn_inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+SIM_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def hn():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2606_27280_amd as hn
+    hn._lib.lib()
+    return hn
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def assert_exact(gi, gs, ri, rs, what=""):
+    gi = np.asarray(gi)
+    gs = np.asarray(gs)
+    bad = np.nonzero(gi != ri)[0]
+    assert bad.size == 0, "%s: %d index mismatches, first q=%d gpu=%d oracle=%d" % (
+        what, bad.size, bad[0], gi[bad[0]], ri[bad[0]])
+    d = np.abs(gs - rs)
+    assert (d <= SIM_TOL).all(), "%s: max |dsim| = %g" % (what, d.max())
+
+
+# ------------------------------------------------------------ scan numerics
+
+@pytest.mark.parametrize("k", [1, 5, 8, 16, 40, 127])
+def test_scan_scores_fp32_within_rounding_bound(hn, k):
+    alpha = 1 / 8
+    db = hn_inputs.make_db(1005, k, alpha, 7, 100 + k)
+    qs = hn_inputs.make_queries(db, k, alpha, 30, 7, 200 + k)
+    say("scan_scores fp32 k=%d n=1005 q=37" % k)
+    ix = hn.Index(dev(db), k, alpha)
+    got = ix.scan_scores(dev(qs), "fp32").cpu().numpy().astype(np.float64)
+    ref = qs[:, :k].astype(np.float64) @ db[:, :k].astype(np.float64).T
+    absprod = np.abs(qs[:, :k]).astype(np.float64) @ np.abs(db[:, :k]).astype(np.float64).T
+    gam = k * 2.0 ** -23 / (1 - k * 2.0 ** -23)
+    err = np.abs(got - ref)
+    assert (err <= gam * absprod + k * 2.0 ** -125 + 1e-15).all(), err.max()
+    ix.close()
+
+
+@pytest.mark.parametrize("k", [8, 16, 30, 64])
+def test_scan_scores_bf16_within_rounding_bound(hn, k):
+    alpha = 1 / 32
+    db = hn_inputs.make_db(999, k, alpha, 5, 300 + k)
+    qs = hn_inputs.make_queries(db, k, alpha, 20, 5, 400 + k)
+    say("scan_scores bf16 k=%d n=999 q=25" % k)
+    ix = hn.Index(dev(db), k, alpha)
+    got = ix.scan_scores(dev(qs), "bf16").cpu().numpy().astype(np.float64)
+    ref = qs[:, :k].astype(np.float64) @ db[:, :k].astype(np.float64).T
+    absprod = np.abs(qs[:, :k]).astype(np.float64) @ np.abs(db[:, :k]).astype(np.float64).T
+    ub = 2.0 ** -8
+    bound = absprod * ((2 * ub + ub * ub) + k * 2.0 ** -23 / (1 - k * 2.0 ** -23) * (1 + ub) ** 2)
+    err = np.abs(got - ref)
+    assert (err <= bound + k * 2.0 ** -125 + 1e-15).all(), (err - bound).max()
+    # and the rounding really happened (this is not the float32 path)
+    assert err.max() > 1e-5
+    ix.close()
+
+
+# ------------------------------------------------------------ exact search
+
+def _check_search(hn, db, qs, k, alpha, precision="fp32", what="", **kw):
+    say("search %s: n=%d k=%d alpha=%g q=%d precision=%s %s" % (
+        what, len(db), k, alpha, len(qs), precision, kw))
+    ix = hn.Index(dev(db), k, alpha, **({"flags": kw.pop("flags")} if "flags" in kw else {}))
+    idx, sim, aux, st = ix.search(dev(qs), precision=precision, aux=True, stats=True, **kw)
+    ref = oracle.bnb_top1(db, qs, k, alpha)
+    assert_exact(idx.cpu().numpy(), sim.cpu().numpy(), ref["idx"], ref["sim"], what)
+    out = {n: t.cpu().numpy() for n, t in aux.items()}
+    ix.close()
+    return ref, out, st
+
+
+def test_workload1_fp32_and_bf16_exact(hn):
+    w = hn_inputs.workload(1)
+    db = w.db()
+    qs = w.queries(db)
+    bi, bs = oracle.bruteforce_top1(db, qs)
+    for prec in ("fp32", "bf16"):
+        ref, aux, st = _check_search(hn, db, qs, w.k, w.alpha, prec, "workload1")
+        assert (ref["idx"] == bi).all()
+        assert st["overflow_queries"] == 0
+        # the seed bound is the canonical sim of a real entry
+        for qi in range(0, len(qs), 17):
+            assert aux["seed_sim"][qi] == oracle.sim(qs[qi], db[aux["seed_idx"][qi]])
+        # survivor counts bracketed by the oracle's exact sets at the GPU's L
+        L = aux["seed_sim"]
+        lo, hi = oracle.survivor_counts(db, qs, w.k, w.alpha,
+                                        L - 2 * aux["slack"] - 2.0 ** -20, L + 2.0 ** -40)
+        assert (hi <= aux["survivors"]).all() and (aux["survivors"] <= lo).all()
+        assert st["survivors"] == int(aux["survivors"].sum())
+
+
+@pytest.mark.parametrize("n,k,alpha,nq", [
+    (1, 8, 1 / 32, 5), (2, 16, 1 / 8, 4), (17, 16, 1 / 8, 3), (100, 1, 0.25, 20),
+    (300, 127, 0.5, 33), (1000, 16, 0.0, 50), (4097, 16, 1 / 8, 1), (5000, 8, 1 / 32, 600),
+    (3001, 40, 1 / 16, 70), (2000, 64, 1 / 4, 17)])
+def test_edge_shapes_exact(hn, n, k, alpha, nq):
+    db = hn_inputs.make_db(n, k, alpha, max(1, n // 64), 1000 + n + k)
+    qs = hn_inputs.make_queries(db, k, alpha, nq - nq // 4, nq // 4, 2000 + n + k)
+    if n >= 8:  # exact ties: duplicated rows
+        db[n - 1] = db[0]
+        db[n // 2] = db[3]
+    for prec in ("fp32", "bf16"):
+        _check_search(hn, db, qs, k, alpha, prec, "edge")
+
+
+def test_tie_rule_golden_on_gpu(hn):
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "tie_rule.json")))
+    db = np.zeros((3, 128), dtype=np.float32)
+    db[:, :4] = np.array(g["db"], dtype=np.float32)
+    q = np.zeros((1, 128), dtype=np.float32)
+    q[0, :4] = g["query"]
+    for prec in ("fp32", "bf16"):
+        ref, aux, _ = _check_search(hn, db, q, g["k"], g["alpha"], prec, "tie-golden",
+                                    flags=hn.HN_BUILD_NO_VALIDATE)
+        assert ref["idx"][0] == g["expected_idx"]
+        assert aux["seed_idx"][0] == g["expected_seed"]
+    say("bruteforce tie-golden")
+    bi, bs = hn.bruteforce_top1(dev(db), dev(q))
+    assert int(bi.cpu()[0]) == g["expected_idx"] and float(bs.cpu()[0]) == g["expected_sim"]
+
+
+def test_duplicates_everywhere_and_overflow_fallback(hn):
+    k, alpha = 16, 1 / 8
+    base = hn_inputs.make_db(64, k, alpha, 2, 77)
+    db = np.tile(base, (40, 1))  # every row repeated 40 times
+    qs = hn_inputs.make_queries(base, k, alpha, 24, 8, 78)
+    ref, aux, st = _check_search(hn, db, qs, k, alpha, "fp32", "dup", survivor_cap=500)
+    assert st["overflow_queries"] > 0
+    assert (ref["idx"] < 64).all()  # smallest index among the copies
+    ref2, aux2, st2 = _check_search(hn, db, qs, k, alpha, "fp32", "dup-nocap")
+    assert st2["overflow_queries"] == 0
+
+
+def test_invalid_inputs(hn):
+    import torch
+    k, alpha = 8, 1 / 32
+    db = hn_inputs.make_db(500, k, alpha, 4, 5)
+    bad = db.copy()
+    bad[123, :k] *= 1.01
+    say("build with an off-norm row")
+    with pytest.raises(hn.HNError) as e:
+        hn.Index(dev(bad), k, alpha)
+    assert e.value.code == -2 and "123" in str(e.value)
+    ix = hn.Index(dev(bad), k, alpha, flags=hn.HN_BUILD_NO_VALIDATE)  # stays exact
+    qs = hn_inputs.make_queries(db, k, alpha, 40, 10, 6)
+    idx, sim = ix.search(dev(qs))
+    ref = oracle.bnb_top1(bad, qs, k, alpha)
+    assert_exact(idx.cpu().numpy(), sim.cpu().numpy(), ref["idx"], ref["sim"], "off-norm")
+    ix.close()
+    nan = db.copy()
+    nan[7, 50] = np.nan
+    say("build with a NaN row")
+    for fl in (0, hn.HN_BUILD_NO_VALIDATE):
+        with pytest.raises(hn.HNError):
+            hn.Index(dev(nan), k, alpha, flags=fl)
+    say("search with a NaN query")
+    ix = hn.Index(dev(db), k, alpha)
+    q2 = qs.copy()
+    q2[3, 0] = np.inf
+    idx, sim = ix.search(dev(q2))
+    idx, sim = idx.cpu().numpy(), sim.cpu().numpy()
+    assert idx[3] == -1 and math.isnan(sim[3])
+    ok = np.arange(len(q2)) != 3
+    ref = oracle.bnb_top1(db, q2[ok], k, alpha)
+    assert_exact(idx[ok], sim[ok], ref["idx"], ref["sim"], "nan-query")
+    e0 = torch.empty(0, 128, dtype=torch.float32, device="cuda:0")
+    i0, s0 = ix.search(e0)
+    assert i0.numel() == 0
+    with pytest.raises(ValueError):
+        ix.search(dev(qs).double())
+    with pytest.raises(hn.HNError):
+        ix.search(dev(qs), precision="fp8")
+    with pytest.raises(hn.HNError):
+        ix.search(dev(qs), beta=0.5)
+    ix.close()
+    with pytest.raises(hn.HNError):
+        hn.Index(dev(db[:, :64]), k, alpha)
+
+
+def test_determinism_configs_and_batch_invariance(hn):
+    w = hn_inputs.workload(1)
+    db = w.db()
+    qs = w.queries(db)
+    ix = hn.Index(dev(db), w.k, w.alpha)
+    dq = dev(qs)
+    say("determinism: default config x3")
+    base = ix.search(dq, aux=True)
+    b_idx, b_sim = base[0].cpu().numpy(), base[1].cpu().numpy()
+    b_surv = base[2]["survivors"].cpu().numpy()
+    for rep in range(2):
+        r = ix.search(dq, aux=True)
+        assert (r[0].cpu().numpy() == b_idx).all()
+        assert np.array_equal(r[1].cpu().numpy().view(np.int64), b_sim.view(np.int64))
+        assert (r[2]["survivors"].cpu().numpy() == b_surv).all()
+    for qt in (1, 2, 4, 8):
+        for cb in (0, 8, 37, 1024):
+            say("determinism: query_tiles=%d chunk_blocks=%d" % (qt, cb))
+            r = ix.search(dq, query_tiles=qt, chunk_blocks=cb, aux=True)
+            assert (r[0].cpu().numpy() == b_idx).all()
+            assert np.array_equal(r[1].cpu().numpy().view(np.int64), b_sim.view(np.int64))
+            assert (r[2]["survivors"].cpu().numpy() == b_surv).all()
+    for lo, hi in ((37, 150), (0, 1), (255, 256), (100, 117)):
+        say("batch invariance: queries[%d:%d]" % (lo, hi))
+        r = ix.search(dev(qs[lo:hi]), aux=True)
+        assert (r[0].cpu().numpy() == b_idx[lo:hi]).all()
+        assert (r[2]["survivors"].cpu().numpy() == b_surv[lo:hi]).all()
+    ix.close()
+
+
+def test_filter_survivor_sets_match_oracle(hn):
+    import torch
+    w = hn_inputs.workload(1)
+    db = w.db()
+    qs = w.queries(db)[:24]
+    ix = hn.Index(dev(db), w.k, w.alpha)
+    say("filter survivors: 24 queries, L from the GPU seed")
+    _, _, aux = ix.search(dev(qs), aux=True)
+    L = aux["seed_sim"]
+    pairs, cnt, slack = ix.filter_survivors(dev(qs), L, cap=1 << 20)
+    assert cnt == pairs.shape[0]
+    pairs = pairs.cpu().numpy()
+    L = L.cpu().numpy()
+    slack = slack.cpu().numpy()
+    for qi in range(len(qs)):
+        got = set(pairs[pairs[:, 0] == qi, 1].tolist())
+        must = set(oracle.survivor_list(db, qs[qi], w.k, w.alpha, L[qi] + 2.0 ** -40).tolist())
+        may = set(oracle.survivor_list(db, qs[qi], w.k, w.alpha,
+                                       L[qi] - 2 * slack[qi] - 2.0 ** -20).tolist())
+        assert must <= got <= may, qi
+    # a lower bound of -inf keeps everything; +inf keeps nothing
+    lo = torch.full((3,), -math.inf, dtype=torch.float64, device="cuda:0")
+    _, c_all, _ = ix.filter_survivors(dev(qs[:3]), lo, cap=0)
+    assert c_all == 3 * len(db)
+    _, c_none, _ = ix.filter_survivors(dev(qs[:3]), -lo, cap=0)
+    assert c_none == 0
+    ix.close()
+
+
+# ------------------------------------------------------------ brute force
+
+@pytest.mark.parametrize("n,nq", [(1, 3), (15, 4), (1000, 33), (4103, 70), (16384, 256)])
+def test_bruteforce_exact(hn, n, nq):
+    db = hn_inputs.make_db(n, 16, 1 / 8, max(1, n // 128), 3000 + n)
+    qs = hn_inputs.make_queries(db, 16, 1 / 8, nq - nq // 3, nq // 3, 3100 + n)
+    if n >= 8:
+        db[n - 2] = db[1]
+    say("bruteforce n=%d q=%d" % (n, nq))
+    gi, gs = hn.bruteforce_top1(dev(db), dev(qs))
+    ri, rs = oracle.bruteforce_top1(db, qs)
+    assert_exact(gi.cpu().numpy(), gs.cpu().numpy(), ri, rs, "bruteforce")
+
+
+def test_bruteforce_all_identical_rows_fallback(hn):
+    row = hn_inputs.make_db(1, 16, 1 / 8, 1, 9)
+    db = np.tile(row, (70000, 1))
+    qs = hn_inputs.make_queries(row, 16, 1 / 8, 2, 1, 10)
+    say("bruteforce identical rows n=70000 q=3 (candidate overflow)")
+    gi, gs = hn.bruteforce_top1(dev(db), dev(qs))
+    assert (gi.cpu().numpy() == 0).all()
+    for qi in range(3):
+        assert gs.cpu().numpy()[qi] == oracle.sim(qs[qi], row[0])
+
+
+# ------------------------------------------------------------ full size
+
+def test_workload2_full_size_sampled(hn):
+    """N = 1,048,576, K = 16, alpha = 1/8, Q = 10,000 in the benchmark's launch
+    configuration.  Every query: HN result == exhaustive GPU result and the
+    sim equals the oracle's canonical sim of the returned entry; a strided
+    sample of 500 queries against the oracle's branch-and-bound."""
+    w = hn_inputs.workload(2)
+    db = w.db()
+    qs = w.queries(db)
+    say("workload2 full: build + search fp32/bf16 + bruteforce")
+    ix = hn.Index(dev(db), w.k, w.alpha)
+    dq = dev(qs)
+    i32, s32, aux, st = ix.search(dq, aux=True, stats=True)
+    i16, s16 = ix.search(dq, precision="bf16")
+    bi, bs = hn.bruteforce_top1(dev(db), dq)
+    i32, s32, i16, s16 = (t.cpu().numpy() for t in (i32, s32, i16, s16))
+    bi, bs = bi.cpu().numpy(), bs.cpu().numpy()
+    assert (i32 == bi).all() and np.array_equal(s32, bs)
+    assert (i16 == bi).all() and np.array_equal(s16, bs)
+    assert st["overflow_queries"] == 0
+    sample = np.arange(0, len(qs), 20)
+    ref = oracle.bnb_top1(db, qs[sample], w.k, w.alpha)
+    assert_exact(i32[sample], s32[sample], ref["idx"], ref["sim"], "workload2-sample")
+    rng = np.random.default_rng(0)
+    for qi in rng.choice(len(qs), 200, replace=False):
+        assert s32[qi] == oracle.sim(qs[qi], db[i32[qi]])
+    sb = np.arange(3, len(qs), 625)
+    ri, rs = oracle.bruteforce_top1(db, qs[sb])
+    assert_exact(bi[sb], bs[sb], ri, rs, "workload2-bruteforce-sample")
+    surv = aux["survivors"].cpu().numpy()
+    L = aux["seed_sim"].cpu().numpy()
+    sl = aux["slack"].cpu().numpy()
+    lo, hi = oracle.survivor_counts(db, qs[sample], w.k, w.alpha,
+                                    L[sample] - 2 * sl[sample] - 2.0 ** -20, L[sample] + 2.0 ** -40)
+    assert (hi <= surv[sample]).all() and (surv[sample] <= lo).all()
+    pruned = 1.0 - surv.mean() / len(db)
+    say("workload2: pruned %.4f%%, survivors/query %.1f" % (100 * pruned, surv.mean()))
+    assert pruned > 0.99
+    ix.close()
