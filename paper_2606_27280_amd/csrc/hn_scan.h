@@ -15,9 +15,9 @@
 // Work decomposition: a work-group of 4 waves owns one query block (WQ query
 // sub-blocks of NQ 16-query tiles) and one chunk of entry blocks; the 4 / WQ
 // waves that share a sub-block interleave over the chunk's entry blocks.
-// Work items are laid out so that consecutive items on one XCD (blockIdx % 8)
-// read the same chunk, keeping it in that XCD's L2 while every query block
-// passes over it.
+// Work items (query block, chunk) are numbered chunk-major and split into 8
+// contiguous ranges, one per XCD (blockIdx % 8), so the work-groups of one XCD
+// pass every query block over the same chunk while it sits in that XCD's L2.
 #pragma once
 
 #include "hn_internal.h"
@@ -49,6 +49,7 @@ struct ScanArgs {
     int64_t cap;
     int32_t *qflag;     // set when a query's pair did not fit
     float *scores;      // store: [q_count][n]
+    unsigned *work;     // 8 per-XCD item counters, zero before the launch
 };
 
 // ------------------------------------------------------------ operand policies
@@ -137,35 +138,63 @@ __device__ __forceinline__ unsigned lane_prefix(unsigned long long m) {
                                      __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-// Append the lane's entries with score >= t (predicate per v) to the pair
-// list: one atomic per wave, positions by ballot + mbcnt prefix counts.
+// Survivor staging: each wave collects (query, entry) pairs in its own LDS
+// buffer and flushes it to the global list with one atomic per batch, written
+// as one contiguous, coalesced run.
+constexpr int kEmitCap = 256;  // pairs per wave buffer (>= 64 lanes x 4 entries)
+
+struct EmitBuf {
+    int2 *pairs;  // LDS [kEmitCap]
+    float *vals;  // LDS [kEmitCap] (window mode)
+    int count;    // wave-uniform
+};
+
 template <bool WithVal>
-__device__ __forceinline__ void emit_pairs(const ScanArgs &A, v4f a, float t, bool qvalid,
-                                           int q, int e0) {
+__device__ __forceinline__ void flush_pairs(const ScanArgs &A, EmitBuf &B) {
+    if (B.count == 0) return;
+    __builtin_amdgcn_wave_barrier();
+    unsigned long long base = 0;
+    if (__lane_id() == 0) base = atomicAdd(A.counter, (unsigned long long)B.count);
+    base = __shfl(base, 0);
+    for (int i = (int)__lane_id(); i < B.count; i += 64) {
+        const int2 pr = B.pairs[i];
+        const unsigned long long pos = base + (unsigned)i;
+        if ((int64_t)pos < A.cap) {
+            A.pairs[pos] = pr;
+            if (WithVal) A.pair_val[pos] = B.vals[i];
+        } else {
+            A.qflag[pr.x] = 1;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    B.count = 0;
+}
+
+// Append the lane's entries with score >= t: ballot per entry slot, positions
+// by popcount + mbcnt prefix counts.
+template <bool WithVal>
+__device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B, v4f a, float t,
+                                           bool qvalid, int q, int e0) {
     bool p0 = qvalid && a[0] >= t, p1 = qvalid && a[1] >= t;
     bool p2 = qvalid && a[2] >= t, p3 = qvalid && a[3] >= t;
     unsigned long long m0 = __ballot(p0), m1 = __ballot(p1), m2 = __ballot(p2),
                        m3 = __ballot(p3);
-    unsigned c0 = __popcll(m0), c1 = __popcll(m1), c2 = __popcll(m2), c3 = __popcll(m3);
-    if (c0 + c1 + c2 + c3 == 0) return;
-    unsigned long long base = 0;
-    if (__lane_id() == 0) base = atomicAdd(A.counter, (unsigned long long)(c0 + c1 + c2 + c3));
-    base = __shfl(base, 0);
+    const int c0 = __popcll(m0), c1 = __popcll(m1), c2 = __popcll(m2), c3 = __popcll(m3);
+    const int total = c0 + c1 + c2 + c3;
+    if (total == 0) return;
+    if (B.count + total > kEmitCap) flush_pairs<WithVal>(A, B);
     const bool pv[4] = {p0, p1, p2, p3};
     const unsigned long long mv[4] = {m0, m1, m2, m3};
-    const unsigned off[4] = {0u, c0, c0 + c1, c0 + c1 + c2};
+    const int off[4] = {0, c0, c0 + c1, c0 + c1 + c2};
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         if (pv[v]) {
-            unsigned long long pos = base + off[v] + lane_prefix(mv[v]);
-            if ((int64_t)pos < A.cap) {
-                A.pairs[pos] = make_int2(q, e0 + v);
-                if (WithVal) A.pair_val[pos] = a[v];
-            } else {
-                A.qflag[q] = 1;
-            }
+            const int pos = B.count + off[v] + (int)lane_prefix(mv[v]);
+            B.pairs[pos] = make_int2(q, e0 + v);
+            if (WithVal) B.vals[pos] = a[v];
         }
     }
+    B.count += total;
 }
 
 // Lexicographic (value desc, index asc) merge; idx < 0 marks "none".
@@ -178,18 +207,14 @@ __device__ __forceinline__ void lex_merge(float &v, int &i, float ov, int oi) {
 
 // ------------------------------------------------------------ the scan kernel
 
+// One work item: query block qb x entry chunk `chunk`.
 template <class Tile, int NQ, int WQ, int MODE>
-__global__ __launch_bounds__(256) void scan_kernel(ScanArgs A) {
+__device__ __forceinline__ void scan_item(const ScanArgs &A, const int chunk, const int qb,
+                                          float (*sh_val)[NQ * 16], int (*sh_idx)[NQ * 16],
+                                          EmitBuf &eb) {
     typedef typename Tile::Elem Elem;
     typedef typename Tile::Frag Frag;
     constexpr int NS = kWaves / WQ;  // waves sharing one query sub-block
-    __shared__ float sh_val[kWaves][NQ * 16];
-    __shared__ int sh_idx[kWaves][NQ * 16];
-
-    const int per_xcd = gridDim.x / kXcds;
-    const int item = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
-    if (item >= A.n_items) return;
-    const int chunk = item / A.n_qb, qb = item % A.n_qb;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
     const int wq = wave % WQ, ws = wave / WQ;
@@ -216,43 +241,78 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs A) {
     const int blk0 = chunk * A.chunk_blocks;
     const int blk1 = min(blk0 + A.chunk_blocks, A.n_blocks);
     const int64_t last_row = A.n - 1;
-    for (int blk = blk0 + ws; blk < blk1; blk += NS) {
-        Frag xf;
-        int64_t row = min((int64_t)blk * 16 + r, last_row);
-        Tile::load(xf, xs + row * A.x_stride + g * Tile::kSlice);
-        const int e0 = blk * 16 + 4 * g;
-        const bool tail = (int64_t)(blk + 1) * 16 > A.n;
+    const Elem *xcol = xs + g * Tile::kSlice;
+    int blk = blk0 + ws;
+    Frag xf, xn;
+    if (blk < blk1) Tile::load(xf, xcol + min((int64_t)blk * 16 + r, last_row) * A.x_stride);
+    for (; blk < blk1; blk += NS) {
+        // prefetch the next block of this wave while the current one computes
+        const int nb = blk + NS;
+        if (nb < blk1) Tile::load(xn, xcol + min((int64_t)nb * 16 + r, last_row) * A.x_stride);
+        v4f acc[NQ];
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
-            v4f acc = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc = Tile::mma(xf, qf[t], acc);
-            if (tail) {
+            const v4f z = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc[t] = Tile::mma(xf, qf[t], z);
+        }
+        const int e0 = blk * 16 + 4 * g;
+        if ((int64_t)(blk + 1) * 16 > A.n) {
+#pragma unroll
+            for (int t = 0; t < NQ; ++t)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    if (e0 + v >= A.n) acc[v] = -INFINITY;
-            }
-            const float mx = fmaxf(fmaxf(acc[0], acc[1]), fmaxf(acc[2], acc[3]));
-            if constexpr (MODE == kArgmax) {
-                if (mx > best[t]) {
-                    best[t] = mx;
+                    if (e0 + v >= A.n) acc[t][v] = -INFINITY;
+        }
+        float mx[NQ];
+#pragma unroll
+        for (int t = 0; t < NQ; ++t)
+            mx[t] = fmaxf(fmaxf(acc[t][0], acc[t][1]), fmaxf(acc[t][2], acc[t][3]));
+        if constexpr (MODE == kArgmax) {
+#pragma unroll
+            for (int t = 0; t < NQ; ++t) {
+                if (mx[t] > best[t]) {
+                    best[t] = mx[t];
                     bblk[t] = blk;
                 }
-            } else if constexpr (MODE == kFilter) {
-                if (__ballot(mx >= thr[t])) emit_pairs<false>(A, acc, thr[t], qid[t] < A.q_count, qid[t], e0);
-            } else if constexpr (MODE == kWindow) {
-                const float nb = fmaxf(best[t], mx);
-                best[t] = nb;
-                const float lim = nb - thr[t];
-                if (__ballot(mx >= lim)) emit_pairs<true>(A, acc, lim, qid[t] < A.q_count, qid[t], e0);
-            } else {
+            }
+        } else if constexpr (MODE == kFilter) {
+            bool any = false;
+#pragma unroll
+            for (int t = 0; t < NQ; ++t) any = any || (mx[t] >= thr[t]);
+            if (__ballot(any)) {
+#pragma unroll
+                for (int t = 0; t < NQ; ++t)
+                    if (__ballot(mx[t] >= thr[t]))
+                        emit_pairs<false>(A, eb, acc[t], thr[t], qid[t] < A.q_count, qid[t], e0);
+            }
+        } else if constexpr (MODE == kWindow) {
+            float lim[NQ];
+            bool any = false;
+#pragma unroll
+            for (int t = 0; t < NQ; ++t) {
+                best[t] = fmaxf(best[t], mx[t]);
+                lim[t] = best[t] - thr[t];
+                any = any || (mx[t] >= lim[t]);
+            }
+            if (__ballot(any)) {
+#pragma unroll
+                for (int t = 0; t < NQ; ++t)
+                    if (__ballot(mx[t] >= lim[t]))
+                        emit_pairs<true>(A, eb, acc[t], lim[t], qid[t] < A.q_count, qid[t], e0);
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < NQ; ++t) {
                 if (qid[t] < A.q_count) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        if (e0 + v < A.n) A.scores[(int64_t)qid[t] * A.n + e0 + v] = acc[v];
+                        if (e0 + v < A.n) A.scores[(int64_t)qid[t] * A.n + e0 + v] = acc[t][v];
                 }
             }
         }
+        xf = xn;
     }
+    if constexpr (MODE == kFilter || MODE == kWindow) flush_pairs<MODE == kWindow>(A, eb);
 
     if constexpr (MODE == kArgmax || MODE == kWindow) {
         // per query: merge the 4 lane groups, then the NS waves of the sub-block
@@ -279,13 +339,47 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs A) {
                 float v = sh_val[wave][t * 16 + r];
                 int i = sh_idx[wave][t * 16 + r];
                 for (int s = 1; s < NS; ++s)
-                    lex_merge(v, i, sh_val[wave + s * WQ][t * 16 + r], sh_idx[wave + s * WQ][t * 16 + r]);
+                    lex_merge(v, i, sh_val[wave + s * WQ][t * 16 + r],
+                              sh_idx[wave + s * WQ][t * 16 + r]);
                 const int q = qid[t];
                 if (q < A.q_pad) {
                     A.part_val[(int64_t)chunk * A.q_pad + q] = v;
                     if (MODE == kArgmax) A.part_idx[(int64_t)chunk * A.q_pad + q] = i;
                 }
             }
+        }
+    }
+}
+
+// Persistent scan: each work-group pulls items from its XCD's range through an
+// atomic counter, then helps the other XCDs' ranges; it exits once every range
+// is exhausted.  Items of one range share entry chunks (see make_plan), so the
+// work-groups of one XCD stream the same chunk through that XCD's L2.
+template <class Tile, int NQ, int WQ, int MODE>
+__global__ __launch_bounds__(256) void scan_kernel(ScanArgs A) {
+    __shared__ float sh_val[kWaves][NQ * 16];
+    __shared__ int sh_idx[kWaves][NQ * 16];
+    __shared__ int sh_item;
+    constexpr bool kEmits = MODE == kFilter || MODE == kWindow;
+    __shared__ int2 sh_pairs[kEmits ? kWaves : 1][kEmits ? kEmitCap : 1];
+    __shared__ float sh_pval[MODE == kWindow ? kWaves : 1][MODE == kWindow ? kEmitCap : 1];
+    EmitBuf eb;
+    eb.pairs = sh_pairs[kEmits ? (threadIdx.x >> 6) : 0];
+    eb.vals = sh_pval[MODE == kWindow ? (threadIdx.x >> 6) : 0];
+    eb.count = 0;
+    const int xcd = (int)(blockIdx.x % kXcds);
+    const int per = (A.n_items + kXcds - 1) / kXcds;
+    for (int hop = 0; hop < kXcds; ++hop) {
+        const int x = (xcd + hop) % kXcds;
+        const int lo = x * per, hi = min(A.n_items, lo + per);
+        if (lo >= hi) continue;
+        while (true) {
+            if (threadIdx.x == 0) sh_item = (int)atomicAdd(&A.work[x], 1u);
+            __syncthreads();
+            const int item = lo + sh_item;
+            __syncthreads();
+            if (item >= hi) break;
+            scan_item<Tile, NQ, WQ, MODE>(A, item / A.n_qb, item % A.n_qb, sh_val, sh_idx, eb);
         }
     }
 }

@@ -37,8 +37,10 @@ __global__ __launch_bounds__(256) void prep_queries(const float *__restrict__ q,
                                                     int64_t q_pad, int k, int w32, int w16,
                                                     float *__restrict__ op32,
                                                     uint16_t *__restrict__ op16,
-                                                    QNorm *__restrict__ qn) {
+                                                    QNorm *__restrict__ qn,
+                                                    unsigned *__restrict__ work) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (work && i < 2 * kXcds) work[i] = 0u;
     if (i >= q_pad) return;
     if (i >= nq) {
         if (op32)
@@ -432,7 +434,6 @@ struct Plan {
     int qb_size() const { return nq * wq * 16; }
     int32_t n_qb = 0, chunk_blocks = 0, n_chunks = 0, n_items = 0;
     int64_t q_pad = 0;
-    unsigned grid = 0;
 };
 
 // Configurations compiled for each operand policy: (NQ, WQ).
@@ -460,15 +461,49 @@ Plan make_plan(int64_t n, int64_t q, int cfg, int chunk_blocks) {
     p.q_pad = (int64_t)p.n_qb * qb;
     const int32_t n_blocks = (int32_t)((n + 15) / 16);
     if (chunk_blocks <= 0) {
-        const int64_t target_items = 2048;
+        const int64_t target_items = 4096;
         int64_t want_chunks = std::max<int64_t>(1, (target_items + p.n_qb - 1) / p.n_qb);
         chunk_blocks = (int32_t)std::max<int64_t>(8, (n_blocks + want_chunks - 1) / want_chunks);
     }
     p.chunk_blocks = std::min<int32_t>(chunk_blocks, n_blocks);
     p.n_chunks = (n_blocks + p.chunk_blocks - 1) / p.chunk_blocks;
     p.n_items = p.n_qb * p.n_chunks;
-    p.grid = (unsigned)((p.n_items + kXcds - 1) / kXcds * kXcds);
     return p;
+}
+
+int cu_count() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v <= 0)
+            v = 256;
+        cached[dev] = v;
+    }
+    return cached[dev];
+}
+
+// Persistent grid: every resident work-group slot once, at most one per item
+// (rounded to whole XCD rounds).
+template <class Tile, int NQ, int WQ, int MODE>
+unsigned persistent_grid(int n_items) {
+    static const int per_cu = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &b, reinterpret_cast<const void *>(&scan_kernel<Tile, NQ, WQ, MODE>), 256, 0) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            b = 1;
+        }
+        return b < 1 ? 1 : b;
+    }();
+    int64_t g = (int64_t)cu_count() * per_cu;
+    const int64_t need = ((int64_t)n_items + kXcds - 1) / kXcds * kXcds;
+    g = std::min(g, need);
+    g = (g + kXcds - 1) / kXcds * kXcds;
+    return (unsigned)std::max<int64_t>(g, kXcds);
 }
 
 template <class Tile, int MODE>
@@ -477,7 +512,8 @@ void launch_scan_cfg(int cfg, const Plan &p, const ScanArgs &A, hipStream_t s) {
 #define HN_CFG(c)                                                                      \
     case c:                                                                            \
         if constexpr (kCfgNQ[c] * Tile::kSlice * sizeof(typename Tile::Elem) / 4 <= 64) \
-            hipLaunchKernelGGL((scan_kernel<Tile, kCfgNQ[c], kCfgWQ[c], MODE>), dim3(p.grid), \
+            hipLaunchKernelGGL((scan_kernel<Tile, kCfgNQ[c], kCfgWQ[c], MODE>),             \
+                               dim3(persistent_grid<Tile, kCfgNQ[c], kCfgWQ[c], MODE>(p.n_items)), \
                                dim3(256), 0, s, A);                                    \
         break;
         HN_CFG(0)
@@ -550,6 +586,7 @@ struct Work {
     int32_t *best_idx = nullptr, *cnt = nullptr, *qflag = nullptr;
     int2 *pairs = nullptr;
     double *psim = nullptr;
+    unsigned *work = nullptr;  // 16 item counters: [0,8) first scan, [8,16) second
     int64_t cap = 0;
 };
 
@@ -597,6 +634,7 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     add(q, 4);
     add(q, 4);
     add(4, 8);
+    add(2 * kXcds, 4);
     add(cap, sizeof(int2));
     add(cap, 8);
     Arena *ar = nullptr;
@@ -618,13 +656,14 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     W.qflag = ar->take<int32_t>(q);
     W.counter = ar->take<unsigned long long>(4);
     W.n_flagged = W.counter + 1;
+    W.work = ar->take<unsigned>(2 * kXcds);
     W.pairs = ar->take<int2>(cap);
     W.psim = ar->take<double>(cap);
 
     {
         ProfScope prof_(s, "prep_queries");
         hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, queries, q,
-                           p.q_pad, ix->k, ix->kp, ix->kb, W.op32, W.op16, W.qn);
+                           p.q_pad, ix->k, ix->kp, ix->kb, W.op32, W.op16, W.qn, W.work);
     }
     HN_HIP(hipGetLastError());
 
@@ -644,6 +683,7 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     A.q_pad = (int32_t)p.q_pad;
     A.part_val = W.part_val;
     A.part_idx = W.part_idx;
+    A.work = W.work;
     if (!lower) {
         rc = launch_scan<kArgmax>(W.precision, W.width, W.cfg, p, A, s);
         if (rc) return rc;
@@ -725,6 +765,7 @@ ScanArgs filter_args(const hn_index *ix, const Work &W, int64_t q, int2 *pairs, 
     A.counter = W.counter;
     A.cap = cap;
     A.qflag = W.qflag;
+    A.work = W.work + kXcds;
     return A;
 }
 
@@ -901,15 +942,16 @@ extern "C" int hn_scan_scores(const hn_index *ix, const float *queries, int64_t 
     const Plan &p = W.plan;
     size_t bytes = ((p.q_pad * ix->kp * 4 + 255) & ~size_t(255)) +
                    ((p.q_pad * ix->kb * 2 + 255) & ~size_t(255)) +
-                   ((p.q_pad * sizeof(QNorm) + 255) & ~size_t(255));
+                   ((p.q_pad * sizeof(QNorm) + 255) & ~size_t(255)) + 256;
     Arena *ar = nullptr;
     int rc = arena_for(stream, bytes, &ar);
     if (rc) return rc;
     W.op32 = ar->take<float>(p.q_pad * ix->kp);
     W.op16 = ar->take<uint16_t>(p.q_pad * ix->kb);
     W.qn = ar->take<QNorm>(p.q_pad);
+    W.work = ar->take<unsigned>(2 * kXcds);
     hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, queries, q,
-                       p.q_pad, ix->k, ix->kp, ix->kb, W.op32, W.op16, W.qn);
+                       p.q_pad, ix->k, ix->kp, ix->kb, W.op32, W.op16, W.qn, W.work);
     ScanArgs A;
     memset(&A, 0, sizeof A);
     A.x = precision == HN_PREC_FP32 ? (const void *)ix->major32 : (const void *)ix->major16;
@@ -925,6 +967,7 @@ extern "C" int hn_scan_scores(const hn_index *ix, const float *queries, int64_t 
     A.q_count = (int32_t)q;
     A.q_pad = (int32_t)p.q_pad;
     A.scores = scores;
+    A.work = W.work;
     return launch_scan<kStore>(precision, W.width, W.cfg, p, A, s);
 }
 
@@ -941,7 +984,12 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     hipStream_t s = (hipStream_t)stream;
     const int cfg = pick_cfg(q, kDim / 4, 2);
     Plan p = make_plan(n, q, cfg, 0);
-    const int64_t cap = std::min<int64_t>(std::max<int64_t>(q * 256, 1 << 16), (int64_t)1 << 26);
+    // the window is relative to each lane's running maximum, so a few
+    // candidates per lane stream and item are expected; the rest overflow
+    // into the exact fallback
+    const int64_t cap = std::min<int64_t>(
+        std::max<int64_t>(q * std::max<int64_t>(1024, 64 * (int64_t)p.n_chunks), 1 << 16),
+        (int64_t)1 << 26);
 
     size_t bytes = 0;
     auto add = [&](size_t count, size_t sz) { bytes += (count * sz + 255) & ~size_t(255); };
@@ -955,6 +1003,7 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     add(q, 4);
     add(q, 4);
     add(4, 8);
+    add(2 * kXcds, 4);
     add(cap, sizeof(int2));
     add(cap, 4);
     add(cap, 8);
@@ -972,6 +1021,7 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     int32_t *qflag = ar->take<int32_t>(q);
     unsigned long long *counter = ar->take<unsigned long long>(4);
     unsigned long long *mu_key = counter + 1;
+    unsigned *work = ar->take<unsigned>(2 * kXcds);
     int2 *pairs = ar->take<int2>(cap);
     float *pair_val = ar->take<float>(cap);
     double *psim = ar->take<double>(cap);
@@ -982,7 +1032,7 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
         hipLaunchKernelGGL(bf_db_norm, dim3(blocks_for(n)), dim3(256), 0, s, db, n, mu_key);
     }
     hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, queries, q,
-                       p.q_pad, kDim - 1, 0, 0, (float *)nullptr, (uint16_t *)nullptr, qn);
+                       p.q_pad, kDim - 1, 0, 0, (float *)nullptr, (uint16_t *)nullptr, qn, work);
     BfPrepArgs P{qn, mu_key, q, p.q_pad, win_scan, win, best_key, best_idx, cnt, qflag, counter};
     {
         ProfScope prof_(s, "bf_prep");
@@ -1010,6 +1060,7 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     A.counter = counter;
     A.cap = cap;
     A.qflag = qflag;
+    A.work = work;
     rc = launch_scan<kWindow>(HN_PREC_FP32, kDim, cfg, p, A, s);
     if (rc) return rc;
     {
