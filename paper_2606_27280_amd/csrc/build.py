@@ -7,7 +7,8 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
-SOURCES = ["hn_index.hip", "hn_search.hip", "hn_profile.hip"]
+SOURCES = ["hn_index.hip", "hn_search.hip", "hn_profile.hip", "hn_scan_f32n.hip",
+           "hn_scan_f32w.hip", "hn_scan_bf16.hip"]
 OUT = os.path.join(PKG, "libhnsearch.so")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -28,8 +29,25 @@ def build(verbose: bool = False) -> str:
             sys.stderr.write(r.stderr)
         return obj
 
-    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+    def check_one(src):
+        # device assembly, checked for barriers inside divergent loops
+        asm = os.path.join(objdir, src + ".s")
+        cmd = ["hipcc", *FLAGS, "-S", "--cuda-device-only", os.path.join(HERE, src), "-o", asm]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("hipcc -S failed for %s:\n%s" % (src, r.stderr[-6000:]))
+        r = subprocess.run([sys.executable, os.path.join(HERE, "check_barriers.py"), asm, "-v"],
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("barrier check failed for %s:\n%s" % (src, r.stdout[-4000:]))
+        return asm
+
+    with ThreadPoolExecutor(max_workers=min(8, 2 * len(SOURCES))) as ex:
+        futs = [ex.submit(compile_one, s) for s in SOURCES]
+        checks = [ex.submit(check_one, s) for s in SOURCES]
+        objs = [f.result() for f in futs]
+        for c in checks:
+            c.result()
     tmp = OUT + ".tmp%d" % os.getpid()
     subprocess.check_call(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs,
                            "-o", tmp])

@@ -18,7 +18,10 @@
 // Work items (query block, chunk) are numbered chunk-major and split into 8
 // contiguous ranges, one per XCD (blockIdx % 8), so the work-groups of one XCD
 // pass every query block over the same chunk while it sits in that XCD's L2.
+// Control flow that decides barriers is kept provably wave-uniform.
 #pragma once
+
+#include <algorithm>
 
 #include "hn_internal.h"
 
@@ -49,7 +52,9 @@ struct ScanArgs {
     int64_t cap;
     int32_t *qflag;     // set when a query's pair did not fit
     float *scores;      // store: [q_count][n]
-    unsigned *work;     // 8 per-XCD item counters, zero before the launch
+    int *redo;          // items to re-run (capacity n_items)
+    unsigned *redo_count;  // zero before the launch
+    const float *init_best;  // window: starting running maximum per query, or NULL
 };
 
 // ------------------------------------------------------------ operand policies
@@ -138,15 +143,19 @@ __device__ __forceinline__ unsigned lane_prefix(unsigned long long m) {
                                      __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-// Survivor staging: each wave collects (query, entry) pairs in its own LDS
-// buffer and flushes it to the global list with one atomic per batch, written
-// as one contiguous, coalesced run.
-constexpr int kEmitCap = 256;  // pairs per wave buffer (>= 64 lanes x 4 entries)
+// Survivor staging.  In the hot loop each wave appends (query, entry) pairs to
+// its own LDS buffer only, so the loop issues no global stores (which would
+// make the compiler drain the prefetch ring); the buffer is flushed to the
+// global list with one atomic per wave at the end of the work item.  A wave
+// whose buffer fills marks the item for a re-run by scan_redo_kernel, which
+// flushes whenever its buffer fills (DIRECT); the set of pairs is the same.
+constexpr int kEmitCap = 512;  // pairs per wave buffer (>= 64 lanes x 4 entries)
 
 struct EmitBuf {
     int2 *pairs;  // LDS [kEmitCap]
     float *vals;  // LDS [kEmitCap] (window mode)
     int count;    // wave-uniform
+    bool full;    // wave-uniform: a pair did not fit (non-direct mode)
 };
 
 template <bool WithVal>
@@ -172,7 +181,7 @@ __device__ __forceinline__ void flush_pairs(const ScanArgs &A, EmitBuf &B) {
 
 // Append the lane's entries with score >= t: ballot per entry slot, positions
 // by popcount + mbcnt prefix counts.
-template <bool WithVal>
+template <bool WithVal, bool Direct>
 __device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B, v4f a, float t,
                                            bool qvalid, int q, int e0) {
     bool p0 = qvalid && a[0] >= t, p1 = qvalid && a[1] >= t;
@@ -182,7 +191,14 @@ __device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B, v4f a,
     const int c0 = __popcll(m0), c1 = __popcll(m1), c2 = __popcll(m2), c3 = __popcll(m3);
     const int total = c0 + c1 + c2 + c3;
     if (total == 0) return;
-    if (B.count + total > kEmitCap) flush_pairs<WithVal>(A, B);
+    if (B.count + total > kEmitCap) {
+        if constexpr (Direct) {
+            flush_pairs<WithVal>(A, B);
+        } else {
+            B.full = true;
+            return;
+        }
+    }
     const bool pv[4] = {p0, p1, p2, p3};
     const unsigned long long mv[4] = {m0, m1, m2, m3};
     const int off[4] = {0, c0, c0 + c1, c0 + c1 + c2};
@@ -208,14 +224,16 @@ __device__ __forceinline__ void lex_merge(float &v, int &i, float ov, int oi) {
 // ------------------------------------------------------------ the scan kernel
 
 // One work item: query block qb x entry chunk `chunk`.
-template <class Tile, int NQ, int WQ, int MODE>
-__device__ __forceinline__ void scan_item(const ScanArgs &A, const int chunk, const int qb,
+template <class Tile, int NQ, int WQ, int MODE, bool Direct>
+__device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
                                           float (*sh_val)[NQ * 16], int (*sh_idx)[NQ * 16],
-                                          EmitBuf &eb) {
+                                          int *sh_full, EmitBuf &eb) {
     typedef typename Tile::Elem Elem;
     typedef typename Tile::Frag Frag;
     constexpr int NS = kWaves / WQ;  // waves sharing one query sub-block
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int chunk = item / A.n_qb, qb = item % A.n_qb;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     const int g = lane >> 4, r = lane & 15;
     const int wq = wave % WQ, ws = wave / WQ;
     const int tile0 = (qb * WQ + wq) * NQ;
@@ -234,7 +252,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int chunk, co
         else
             Tile::zero(qf[t]);
         thr[t] = (MODE == kFilter || MODE == kWindow) ? A.thr[qid[t]] : 0.0f;
-        best[t] = -INFINITY;
+        best[t] = (MODE == kWindow && A.init_best) ? A.init_best[qid[t]] : -INFINITY;
         bblk[t] = -1;
     }
 
@@ -242,77 +260,127 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int chunk, co
     const int blk1 = min(blk0 + A.chunk_blocks, A.n_blocks);
     const int64_t last_row = A.n - 1;
     const Elem *xcol = xs + g * Tile::kSlice;
-    int blk = blk0 + ws;
-    Frag xf, xn;
-    if (blk < blk1) Tile::load(xf, xcol + min((int64_t)blk * 16 + r, last_row) * A.x_stride);
-    for (; blk < blk1; blk += NS) {
-        // prefetch the next block of this wave while the current one computes
-        const int nb = blk + NS;
-        if (nb < blk1) Tile::load(xn, xcol + min((int64_t)nb * 16 + r, last_row) * A.x_stride);
-        v4f acc[NQ];
+    // Two register groups of PF entry blocks each: while one group is being
+    // computed the other one is loading.  Every slot is loaded on every step
+    // (past the item's end the address is clamped to its last block), so the
+    // loads in flight at any point are a fixed, whole group.
+    constexpr int kFragRegs = Tile::kSlice * (int)sizeof(Elem) / 4;
+    constexpr int PF = kFragRegs <= 2 ? 8 : (kFragRegs <= 4 ? 4 : 1);
+    const int blk_last = max(blk1 - 1, 0);
+    auto load_group = [&](Frag (&xg)[PF], int gbase) {
 #pragma unroll
-        for (int t = 0; t < NQ; ++t) {
-            const v4f z = {0.0f, 0.0f, 0.0f, 0.0f};
-            acc[t] = Tile::mma(xf, qf[t], z);
+        for (int j = 0; j < PF; ++j) {
+            const int b = min(gbase + j * NS, blk_last);
+            Tile::load(xg[j], xcol + min((int64_t)b * 16 + r, last_row) * A.x_stride);
         }
-        const int e0 = blk * 16 + 4 * g;
-        if ((int64_t)(blk + 1) * 16 > A.n) {
+    };
+    auto compute_group = [&](const Frag (&xg)[PF], int gbase) {
 #pragma unroll
-            for (int t = 0; t < NQ; ++t)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    if (e0 + v >= A.n) acc[t][v] = -INFINITY;
-        }
-        float mx[NQ];
-#pragma unroll
-        for (int t = 0; t < NQ; ++t)
-            mx[t] = fmaxf(fmaxf(acc[t][0], acc[t][1]), fmaxf(acc[t][2], acc[t][3]));
-        if constexpr (MODE == kArgmax) {
+        for (int j = 0; j < PF; ++j) {
+            const int blk = gbase + j * NS;
+            if (blk >= blk1) break;
+            v4f acc[NQ];
 #pragma unroll
             for (int t = 0; t < NQ; ++t) {
-                if (mx[t] > best[t]) {
-                    best[t] = mx[t];
-                    bblk[t] = blk;
-                }
+                const v4f z = {0.0f, 0.0f, 0.0f, 0.0f};
+                acc[t] = Tile::mma(xg[j], qf[t], z);
             }
-        } else if constexpr (MODE == kFilter) {
-            bool any = false;
-#pragma unroll
-            for (int t = 0; t < NQ; ++t) any = any || (mx[t] >= thr[t]);
-            if (__ballot(any)) {
+            const int e0 = blk * 16 + 4 * g;
+            if ((int64_t)(blk + 1) * 16 > A.n) {
 #pragma unroll
                 for (int t = 0; t < NQ; ++t)
-                    if (__ballot(mx[t] >= thr[t]))
-                        emit_pairs<false>(A, eb, acc[t], thr[t], qid[t] < A.q_count, qid[t], e0);
-            }
-        } else if constexpr (MODE == kWindow) {
-            float lim[NQ];
-            bool any = false;
-#pragma unroll
-            for (int t = 0; t < NQ; ++t) {
-                best[t] = fmaxf(best[t], mx[t]);
-                lim[t] = best[t] - thr[t];
-                any = any || (mx[t] >= lim[t]);
-            }
-            if (__ballot(any)) {
-#pragma unroll
-                for (int t = 0; t < NQ; ++t)
-                    if (__ballot(mx[t] >= lim[t]))
-                        emit_pairs<true>(A, eb, acc[t], lim[t], qid[t] < A.q_count, qid[t], e0);
-            }
-        } else {
-#pragma unroll
-            for (int t = 0; t < NQ; ++t) {
-                if (qid[t] < A.q_count) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        if (e0 + v < A.n) A.scores[(int64_t)qid[t] * A.n + e0 + v] = acc[t][v];
+                        if (e0 + v >= A.n) acc[t][v] = -INFINITY;
+            }
+            float mx[NQ];
+#pragma unroll
+            for (int t = 0; t < NQ; ++t)
+                mx[t] = fmaxf(fmaxf(acc[t][0], acc[t][1]), fmaxf(acc[t][2], acc[t][3]));
+            if constexpr (MODE == kArgmax) {
+#pragma unroll
+                for (int t = 0; t < NQ; ++t) {
+                    if (mx[t] > best[t]) {
+                        best[t] = mx[t];
+                        bblk[t] = blk;
+                    }
+                }
+            } else if constexpr (MODE == kFilter) {
+                bool any = false;
+#pragma unroll
+                for (int t = 0; t < NQ; ++t) any = any || (mx[t] >= thr[t]);
+                if (__ballot(any)) {
+#pragma unroll
+                    for (int t = 0; t < NQ; ++t)
+                        if (__ballot(mx[t] >= thr[t]))
+                            emit_pairs<false, Direct>(A, eb, acc[t], thr[t], qid[t] < A.q_count,
+                                                      qid[t], e0);
+                }
+            } else if constexpr (MODE == kWindow) {
+                float lim[NQ];
+                bool any = false;
+#pragma unroll
+                for (int t = 0; t < NQ; ++t) {
+                    best[t] = fmaxf(best[t], mx[t]);
+                    lim[t] = best[t] - thr[t];
+                    any = any || (mx[t] >= lim[t]);
+                }
+                if (__ballot(any)) {
+#pragma unroll
+                    for (int t = 0; t < NQ; ++t)
+                        if (__ballot(mx[t] >= lim[t]))
+                            emit_pairs<true, Direct>(A, eb, acc[t], lim[t], qid[t] < A.q_count,
+                                                     qid[t], e0);
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < NQ; ++t) {
+                    if (qid[t] < A.q_count) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            if (e0 + v < A.n) A.scores[(int64_t)qid[t] * A.n + e0 + v] = acc[t][v];
+                    }
                 }
             }
         }
-        xf = xn;
+    };
+    constexpr int kStep = PF * NS;  // blocks per group for this wave
+    // The scheduling barriers keep each group's loads ahead of the other
+    // group's compute, so they have a whole compute phase to land.
+    Frag xa[PF], xb[PF];
+    load_group(xa, blk0 + ws);
+    for (int base = blk0 + ws; base < blk1; base += 2 * kStep) {
+        load_group(xb, base + kStep);
+        __builtin_amdgcn_sched_barrier(0);
+        compute_group(xa, base);
+        __builtin_amdgcn_sched_barrier(0);
+        if (base + kStep >= blk1) break;
+        load_group(xa, base + 2 * kStep);
+        __builtin_amdgcn_sched_barrier(0);
+        compute_group(xb, base + kStep);
+        __builtin_amdgcn_sched_barrier(0);
     }
-    if constexpr (MODE == kFilter || MODE == kWindow) flush_pairs<MODE == kWindow>(A, eb);
+    if constexpr (MODE == kFilter || MODE == kWindow) {
+        if constexpr (Direct) {
+            flush_pairs<MODE == kWindow>(A, eb);
+        } else {
+            // flush only if no wave of the item overflowed; else re-run it.
+            // The decision is made uniform explicitly: a branch the compiler
+            // took as divergent would structure the item loop (which holds
+            // barriers) as a divergent loop.
+            if (lane == 0) sh_full[wave] = eb.full ? 1 : 0;
+            __syncthreads();
+            const bool redo =
+                __builtin_amdgcn_readfirstlane(sh_full[0] | sh_full[1] | sh_full[2] | sh_full[3]) != 0;
+            if (!redo) {
+                flush_pairs<MODE == kWindow>(A, eb);
+            } else if (threadIdx.x == 0) {
+                A.redo[atomicAdd(A.redo_count, 1u)] = item;
+            }
+            eb.count = 0;
+            eb.full = false;
+        }
+    }
 
     if constexpr (MODE == kArgmax || MODE == kWindow) {
         // per query: merge the 4 lane groups, then the NS waves of the sub-block
@@ -351,37 +419,177 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int chunk, co
     }
 }
 
-// Persistent scan: each work-group pulls items from its XCD's range through an
-// atomic counter, then helps the other XCDs' ranges; it exits once every range
-// is exhausted.  Items of one range share entry chunks (see make_plan), so the
-// work-groups of one XCD stream the same chunk through that XCD's L2.
+#define HN_SCAN_SHARED(NQ, MODE)                                                          \
+    __shared__ float sh_val[kWaves][NQ * 16];                                             \
+    __shared__ int sh_idx[kWaves][NQ * 16];                                               \
+    __shared__ int sh_full[kWaves];                                                       \
+    constexpr bool kEmits = MODE == kFilter || MODE == kWindow;                           \
+    __shared__ int2 sh_pairs[kEmits ? kWaves : 1][kEmits ? kEmitCap : 1];                 \
+    __shared__ float sh_pval[MODE == kWindow ? kWaves : 1][MODE == kWindow ? kEmitCap : 1]; \
+    EmitBuf eb;                                                                           \
+    eb.pairs = sh_pairs[kEmits ? (threadIdx.x >> 6) : 0];                                 \
+    eb.vals = sh_pval[MODE == kWindow ? (threadIdx.x >> 6) : 0];                          \
+    eb.count = 0;                                                                         \
+    eb.full = false;
+
+// Persistent scan with a static, XCD-ranged item assignment: the items are
+// split into 8 contiguous ranges, one per XCD (blockIdx % 8), and the
+// work-groups of an XCD take their range round-robin, so at any time they work
+// on neighbouring items, which share entry chunks (see make_plan) in that XCD's
+// L2.  The item loop depends only on blockIdx and gridDim: it is uniform, so
+// the barriers inside scan_item are reached by every wave the same number of
+// times.
 template <class Tile, int NQ, int WQ, int MODE>
 __global__ __launch_bounds__(256) void scan_kernel(ScanArgs A) {
-    __shared__ float sh_val[kWaves][NQ * 16];
-    __shared__ int sh_idx[kWaves][NQ * 16];
-    __shared__ int sh_item;
-    constexpr bool kEmits = MODE == kFilter || MODE == kWindow;
-    __shared__ int2 sh_pairs[kEmits ? kWaves : 1][kEmits ? kEmitCap : 1];
-    __shared__ float sh_pval[MODE == kWindow ? kWaves : 1][MODE == kWindow ? kEmitCap : 1];
-    EmitBuf eb;
-    eb.pairs = sh_pairs[kEmits ? (threadIdx.x >> 6) : 0];
-    eb.vals = sh_pval[MODE == kWindow ? (threadIdx.x >> 6) : 0];
-    eb.count = 0;
-    const int xcd = (int)(blockIdx.x % kXcds);
+    HN_SCAN_SHARED(NQ, MODE)
+    const int groups_per_xcd = (int)gridDim.x / kXcds;
+    const int x = (int)(blockIdx.x % kXcds), w = (int)(blockIdx.x / kXcds);
     const int per = (A.n_items + kXcds - 1) / kXcds;
-    for (int hop = 0; hop < kXcds; ++hop) {
-        const int x = (xcd + hop) % kXcds;
-        const int lo = x * per, hi = min(A.n_items, lo + per);
-        if (lo >= hi) continue;
-        while (true) {
-            if (threadIdx.x == 0) sh_item = (int)atomicAdd(&A.work[x], 1u);
-            __syncthreads();
-            const int item = lo + sh_item;
-            __syncthreads();
-            if (item >= hi) break;
-            scan_item<Tile, NQ, WQ, MODE>(A, item / A.n_qb, item % A.n_qb, sh_val, sh_idx, eb);
+    const int lo = x * per, hi = min(A.n_items, lo + per);
+    for (int item = lo + w; item < hi; item += groups_per_xcd)
+        scan_item<Tile, NQ, WQ, MODE, false>(A, item, sh_val, sh_idx, sh_full, eb);
+}
+
+// Re-runs the items whose survivor buffers overflowed, flushing as it goes.
+template <class Tile, int NQ, int WQ, int MODE>
+__global__ __launch_bounds__(256) void scan_redo_kernel(ScanArgs A) {
+    HN_SCAN_SHARED(NQ, MODE)
+    const unsigned n = __builtin_amdgcn_readfirstlane(*A.redo_count);
+    for (unsigned r = blockIdx.x; r < n; r += gridDim.x)
+        scan_item<Tile, NQ, WQ, MODE, true>(A, __builtin_amdgcn_readfirstlane(A.redo[r]), sh_val,
+                                            sh_idx, sh_full, eb);
+}
+
+struct Plan {
+    int nq = 4, wq = 4;  // 16-query tiles per wave, query sub-blocks per group
+    int qb_size() const { return nq * wq * 16; }
+    int32_t n_qb = 0, chunk_blocks = 0, n_chunks = 0, n_items = 0;
+    int64_t q_pad = 0;
+};
+
+// Configurations compiled for each operand policy: (NQ, WQ).
+constexpr int kNumCfg = 6;
+constexpr int kCfgNQ[kNumCfg] = {1, 2, 4, 2, 4, 8};
+constexpr int kCfgWQ[kNumCfg] = {1, 1, 1, 4, 4, 4};
+
+inline int pick_cfg(int64_t q, int slice_regs, int forced_nq) {
+    int best = 0;
+    for (int c = 0; c < kNumCfg; ++c) {
+        if (kCfgNQ[c] * slice_regs > 64) continue;
+        if (forced_nq > 0 && kCfgNQ[c] != forced_nq) continue;
+        best = c;
+        if ((int64_t)kCfgNQ[c] * kCfgWQ[c] * 16 >= q) break;
+    }
+    return best;
+}
+
+inline Plan make_plan(int64_t n, int64_t q, int cfg, int chunk_blocks) {
+    Plan p;
+    p.nq = kCfgNQ[cfg];
+    p.wq = kCfgWQ[cfg];
+    const int64_t qb = p.qb_size();
+    p.n_qb = (int32_t)((q + qb - 1) / qb);
+    p.q_pad = (int64_t)p.n_qb * qb;
+    const int32_t n_blocks = (int32_t)((n + 15) / 16);
+    if (chunk_blocks <= 0) {
+        const int64_t target_items = 16384;
+        int64_t want_chunks = std::max<int64_t>(1, (target_items + p.n_qb - 1) / p.n_qb);
+        chunk_blocks = (int32_t)std::max<int64_t>(8, (n_blocks + want_chunks - 1) / want_chunks);
+    }
+    p.chunk_blocks = std::min<int32_t>(chunk_blocks, n_blocks);
+    p.n_chunks = (n_blocks + p.chunk_blocks - 1) / p.chunk_blocks;
+    p.n_items = p.n_qb * p.n_chunks;
+    return p;
+}
+
+inline int cu_count() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v <= 0)
+            v = 256;
+        cached[dev] = v;
+    }
+    return cached[dev];
+}
+
+// Persistent grid: every resident work-group slot once, at most one per item
+// of the largest XCD range (rounded to whole XCD rounds).
+template <class Tile, int NQ, int WQ, int MODE>
+inline unsigned persistent_grid(int n_items) {
+    static const int per_cu = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &b, reinterpret_cast<const void *>(&scan_kernel<Tile, NQ, WQ, MODE>), 256, 0) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            b = 1;
         }
+        return b < 1 ? 1 : b;
+    }();
+    int64_t g = (int64_t)cu_count() * per_cu;
+    const int64_t need = ((int64_t)n_items + kXcds - 1) / kXcds * kXcds;  // 8 x range size
+    g = std::min(g, need);
+    g = (g + kXcds - 1) / kXcds * kXcds;
+    return (unsigned)std::max<int64_t>(g, kXcds);
+}
+
+template <class Tile, int MODE, int C>
+inline void launch_one(const Plan &p, const ScanArgs &A, hipStream_t s) {
+    if constexpr (kCfgNQ[C] * Tile::kSlice * sizeof(typename Tile::Elem) / 4 <= 64) {
+        hipLaunchKernelGGL((scan_kernel<Tile, kCfgNQ[C], kCfgWQ[C], MODE>),
+                           dim3(persistent_grid<Tile, kCfgNQ[C], kCfgWQ[C], MODE>(p.n_items)),
+                           dim3(256), 0, s, A);
+        if constexpr (MODE == kFilter || MODE == kWindow)
+            hipLaunchKernelGGL((scan_redo_kernel<Tile, kCfgNQ[C], kCfgWQ[C], MODE>), dim3(256),
+                               dim3(256), 0, s, A);
     }
 }
+
+template <class Tile, int MODE>
+inline void launch_cfgs(int cfg, const Plan &p, const ScanArgs &A, hipStream_t s) {
+    switch (cfg) {
+        case 0: launch_one<Tile, MODE, 0>(p, A, s); break;
+        case 1: launch_one<Tile, MODE, 1>(p, A, s); break;
+        case 2: launch_one<Tile, MODE, 2>(p, A, s); break;
+        case 3: launch_one<Tile, MODE, 3>(p, A, s); break;
+        case 4: launch_one<Tile, MODE, 4>(p, A, s); break;
+        case 5: launch_one<Tile, MODE, 5>(p, A, s); break;
+    }
+}
+
+// Instantiated modes: argmax and filter for every tile and configuration;
+// store (the score buffer) for configuration 0; the window mode only for the
+// 128-wide float32 tile of the exhaustive scan.  Returns nonzero if the
+// requested combination is not compiled.
+template <class Tile, bool Window>
+inline int launch_tile(int mode, int cfg, const Plan &p, const ScanArgs &A, hipStream_t s) {
+    switch (mode) {
+        case kArgmax: launch_cfgs<Tile, kArgmax>(cfg, p, A, s); return 0;
+        case kFilter: launch_cfgs<Tile, kFilter>(cfg, p, A, s); return 0;
+        case kStore:
+            if (cfg != 0) return 1;
+            launch_one<Tile, kStore, 0>(p, A, s);
+            return 0;
+        case kWindow:
+            if constexpr (Window) {
+                launch_cfgs<Tile, kWindow>(cfg, p, A, s);
+                return 0;
+            }
+            return 1;
+    }
+    return 1;
+}
+
+// Per-precision launchers, each compiled in its own translation unit.
+int launch_scan_f32_narrow(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
+                           hipStream_t s);  // widths 4, 8, 16
+int launch_scan_f32_wide(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
+                         hipStream_t s);    // widths 32, 64, 128
+int launch_scan_bf16(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
+                     hipStream_t s);        // widths 16, 32, 64, 128
 
 }  // namespace hn

@@ -16,6 +16,9 @@ constexpr double kU32 = 1.0 / 8388608.0;               // 2^-23 (covers RNE and 
 constexpr double kU64 = 1.0 / 9007199254740992.0;      // 2^-53
 constexpr double kUbf16 = 1.0 / 256.0;                 // 2^-8, bf16 round-to-nearest
 constexpr int kIdxNone = 0x7fffffff;
+// Scan bookkeeping words zeroed by prep_queries: [0,8) item counters of the
+// first scan, [8,16) of the second, 16 and 17 their redo counts.
+constexpr int kWorkWords = 32;
 
 // ---------------------------------------------------------------- queries
 
@@ -40,7 +43,7 @@ __global__ __launch_bounds__(256) void prep_queries(const float *__restrict__ q,
                                                     QNorm *__restrict__ qn,
                                                     unsigned *__restrict__ work) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (work && i < 2 * kXcds) work[i] = 0u;
+    if (work && i < kWorkWords) work[i] = 0u;
     if (i >= q_pad) return;
     if (i >= nq) {
         if (op32)
@@ -272,7 +275,8 @@ __global__ __launch_bounds__(256) void fallback_kernel(FallbackArgs F) {
     __shared__ int si[256];
     __shared__ int sc[256];
     for (int64_t qi = blockIdx.x; qi < F.q; qi += gridDim.x) {
-        if (!F.qflag[qi]) continue;
+        // uniform: the reduction below holds barriers
+        if (!__builtin_amdgcn_readfirstlane(F.qflag[qi])) continue;
         const float *qv = F.queries + qi * kDim;
         const QNorm qn = F.qn[qi];
         double lim = -INFINITY;
@@ -429,103 +433,6 @@ unsigned blocks_for(int64_t items, int per = 256) {
     return (unsigned)std::max<int64_t>(1, (items + per - 1) / per);
 }
 
-struct Plan {
-    int nq = 4, wq = 4;  // 16-query tiles per wave, query sub-blocks per group
-    int qb_size() const { return nq * wq * 16; }
-    int32_t n_qb = 0, chunk_blocks = 0, n_chunks = 0, n_items = 0;
-    int64_t q_pad = 0;
-};
-
-// Configurations compiled for each operand policy: (NQ, WQ).
-constexpr int kNumCfg = 6;
-constexpr int kCfgNQ[kNumCfg] = {1, 2, 4, 2, 4, 8};
-constexpr int kCfgWQ[kNumCfg] = {1, 1, 1, 4, 4, 4};
-
-int pick_cfg(int64_t q, int slice_regs, int forced_nq) {
-    int best = 0;
-    for (int c = 0; c < kNumCfg; ++c) {
-        if (kCfgNQ[c] * slice_regs > 64) continue;
-        if (forced_nq > 0 && kCfgNQ[c] != forced_nq) continue;
-        best = c;
-        if ((int64_t)kCfgNQ[c] * kCfgWQ[c] * 16 >= q) break;
-    }
-    return best;
-}
-
-Plan make_plan(int64_t n, int64_t q, int cfg, int chunk_blocks) {
-    Plan p;
-    p.nq = kCfgNQ[cfg];
-    p.wq = kCfgWQ[cfg];
-    const int64_t qb = p.qb_size();
-    p.n_qb = (int32_t)((q + qb - 1) / qb);
-    p.q_pad = (int64_t)p.n_qb * qb;
-    const int32_t n_blocks = (int32_t)((n + 15) / 16);
-    if (chunk_blocks <= 0) {
-        const int64_t target_items = 4096;
-        int64_t want_chunks = std::max<int64_t>(1, (target_items + p.n_qb - 1) / p.n_qb);
-        chunk_blocks = (int32_t)std::max<int64_t>(8, (n_blocks + want_chunks - 1) / want_chunks);
-    }
-    p.chunk_blocks = std::min<int32_t>(chunk_blocks, n_blocks);
-    p.n_chunks = (n_blocks + p.chunk_blocks - 1) / p.chunk_blocks;
-    p.n_items = p.n_qb * p.n_chunks;
-    return p;
-}
-
-int cu_count() {
-    static int cached[64] = {0};
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-    if (!cached[dev]) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            v <= 0)
-            v = 256;
-        cached[dev] = v;
-    }
-    return cached[dev];
-}
-
-// Persistent grid: every resident work-group slot once, at most one per item
-// (rounded to whole XCD rounds).
-template <class Tile, int NQ, int WQ, int MODE>
-unsigned persistent_grid(int n_items) {
-    static const int per_cu = [] {
-        int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &b, reinterpret_cast<const void *>(&scan_kernel<Tile, NQ, WQ, MODE>), 256, 0) !=
-            hipSuccess) {
-            (void)hipGetLastError();
-            b = 1;
-        }
-        return b < 1 ? 1 : b;
-    }();
-    int64_t g = (int64_t)cu_count() * per_cu;
-    const int64_t need = ((int64_t)n_items + kXcds - 1) / kXcds * kXcds;
-    g = std::min(g, need);
-    g = (g + kXcds - 1) / kXcds * kXcds;
-    return (unsigned)std::max<int64_t>(g, kXcds);
-}
-
-template <class Tile, int MODE>
-void launch_scan_cfg(int cfg, const Plan &p, const ScanArgs &A, hipStream_t s) {
-    switch (cfg) {
-#define HN_CFG(c)                                                                      \
-    case c:                                                                            \
-        if constexpr (kCfgNQ[c] * Tile::kSlice * sizeof(typename Tile::Elem) / 4 <= 64) \
-            hipLaunchKernelGGL((scan_kernel<Tile, kCfgNQ[c], kCfgWQ[c], MODE>),             \
-                               dim3(persistent_grid<Tile, kCfgNQ[c], kCfgWQ[c], MODE>(p.n_items)), \
-                               dim3(256), 0, s, A);                                    \
-        break;
-        HN_CFG(0)
-        HN_CFG(1)
-        HN_CFG(2)
-        HN_CFG(3)
-        HN_CFG(4)
-        HN_CFG(5)
-#undef HN_CFG
-    }
-}
-
 // precision 0: float32 stream of width w; 1: bf16 stream of width w.
 const char *scan_tag(int mode, int precision) {
     static const char *const tags[4][2] = {
@@ -540,27 +447,15 @@ template <int MODE>
 int launch_scan(int precision, int w, int cfg, const Plan &p, const ScanArgs &A,
                 hipStream_t s) {
     ProfScope prof(s, scan_tag(MODE, precision));
-    if (precision == HN_PREC_FP32) {
-        switch (w) {
-            case 4: launch_scan_cfg<F32Tile<4>, MODE>(cfg, p, A, s); break;
-            case 8: launch_scan_cfg<F32Tile<8>, MODE>(cfg, p, A, s); break;
-            case 16: launch_scan_cfg<F32Tile<16>, MODE>(cfg, p, A, s); break;
-            case 32: launch_scan_cfg<F32Tile<32>, MODE>(cfg, p, A, s); break;
-            case 64: launch_scan_cfg<F32Tile<64>, MODE>(cfg, p, A, s); break;
-            case 128: launch_scan_cfg<F32Tile<128>, MODE>(cfg, p, A, s); break;
-            default: return fail(HN_ERR_INVALID_ARG, "bad stream width %d", w);
-        }
-    } else if (precision == HN_PREC_BF16) {
-        switch (w) {
-            case 16: launch_scan_cfg<BF16Tile<16>, MODE>(cfg, p, A, s); break;
-            case 32: launch_scan_cfg<BF16Tile<32>, MODE>(cfg, p, A, s); break;
-            case 64: launch_scan_cfg<BF16Tile<64>, MODE>(cfg, p, A, s); break;
-            case 128: launch_scan_cfg<BF16Tile<128>, MODE>(cfg, p, A, s); break;
-            default: return fail(HN_ERR_INVALID_ARG, "bad stream width %d", w);
-        }
-    } else {
+    int rc;
+    if (precision == HN_PREC_FP32)
+        rc = w <= 16 ? launch_scan_f32_narrow(MODE, w, cfg, p, A, s)
+                     : launch_scan_f32_wide(MODE, w, cfg, p, A, s);
+    else if (precision == HN_PREC_BF16)
+        rc = launch_scan_bf16(MODE, w, cfg, p, A, s);
+    else
         return fail(HN_ERR_UNSUPPORTED, "precision %d is not available", precision);
-    }
+    if (rc) return fail(HN_ERR_INVALID_ARG, "no scan kernel for mode %d width %d config %d", MODE, w, cfg);
     HN_HIP(hipGetLastError());
     return HN_OK;
 }
@@ -586,7 +481,8 @@ struct Work {
     int32_t *best_idx = nullptr, *cnt = nullptr, *qflag = nullptr;
     int2 *pairs = nullptr;
     double *psim = nullptr;
-    unsigned *work = nullptr;  // 16 item counters: [0,8) first scan, [8,16) second
+    unsigned *work = nullptr;  // kWorkWords scan counters (see kWorkWords)
+    int *redo = nullptr;       // [n_items] items to re-run
     int64_t cap = 0;
 };
 
@@ -634,7 +530,8 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     add(q, 4);
     add(q, 4);
     add(4, 8);
-    add(2 * kXcds, 4);
+    add(kWorkWords, 4);
+    add(p.n_items, 4);
     add(cap, sizeof(int2));
     add(cap, 8);
     Arena *ar = nullptr;
@@ -656,7 +553,8 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     W.qflag = ar->take<int32_t>(q);
     W.counter = ar->take<unsigned long long>(4);
     W.n_flagged = W.counter + 1;
-    W.work = ar->take<unsigned>(2 * kXcds);
+    W.work = ar->take<unsigned>(kWorkWords);
+    W.redo = ar->take<int>(p.n_items);
     W.pairs = ar->take<int2>(cap);
     W.psim = ar->take<double>(cap);
 
@@ -683,7 +581,8 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     A.q_pad = (int32_t)p.q_pad;
     A.part_val = W.part_val;
     A.part_idx = W.part_idx;
-    A.work = W.work;
+    A.redo = W.redo;
+    A.redo_count = W.work + 2 * kXcds;
     if (!lower) {
         rc = launch_scan<kArgmax>(W.precision, W.width, W.cfg, p, A, s);
         if (rc) return rc;
@@ -765,7 +664,8 @@ ScanArgs filter_args(const hn_index *ix, const Work &W, int64_t q, int2 *pairs, 
     A.counter = W.counter;
     A.cap = cap;
     A.qflag = W.qflag;
-    A.work = W.work + kXcds;
+    A.redo = W.redo;
+    A.redo_count = W.work + 2 * kXcds + 1;
     return A;
 }
 
@@ -942,14 +842,16 @@ extern "C" int hn_scan_scores(const hn_index *ix, const float *queries, int64_t 
     const Plan &p = W.plan;
     size_t bytes = ((p.q_pad * ix->kp * 4 + 255) & ~size_t(255)) +
                    ((p.q_pad * ix->kb * 2 + 255) & ~size_t(255)) +
-                   ((p.q_pad * sizeof(QNorm) + 255) & ~size_t(255)) + 256;
+                   ((p.q_pad * sizeof(QNorm) + 255) & ~size_t(255)) + 256 +
+                   ((p.n_items * 4 + 255) & ~size_t(255));
     Arena *ar = nullptr;
     int rc = arena_for(stream, bytes, &ar);
     if (rc) return rc;
     W.op32 = ar->take<float>(p.q_pad * ix->kp);
     W.op16 = ar->take<uint16_t>(p.q_pad * ix->kb);
     W.qn = ar->take<QNorm>(p.q_pad);
-    W.work = ar->take<unsigned>(2 * kXcds);
+    W.work = ar->take<unsigned>(kWorkWords);
+    W.redo = ar->take<int>(p.n_items);
     hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, queries, q,
                        p.q_pad, ix->k, ix->kp, ix->kb, W.op32, W.op16, W.qn, W.work);
     ScanArgs A;
@@ -967,7 +869,8 @@ extern "C" int hn_scan_scores(const hn_index *ix, const float *queries, int64_t 
     A.q_count = (int32_t)q;
     A.q_pad = (int32_t)p.q_pad;
     A.scores = scores;
-    A.work = W.work;
+    A.redo = W.redo;
+    A.redo_count = W.work + 2 * kXcds;
     return launch_scan<kStore>(precision, W.width, W.cfg, p, A, s);
 }
 
@@ -984,17 +887,21 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     hipStream_t s = (hipStream_t)stream;
     const int cfg = pick_cfg(q, kDim / 4, 2);
     Plan p = make_plan(n, q, cfg, 0);
-    // the window is relative to each lane's running maximum, so a few
-    // candidates per lane stream and item are expected; the rest overflow
-    // into the exact fallback
+    // A prefix pass (one chunk of the first n_pre rows) gives each query a
+    // starting running maximum: a real scan score, so never above the final
+    // maximum, and far fewer near-record candidates in the main pass.
+    const int64_t n_pre = std::min<int64_t>(n, 4096);
+    Plan pp = make_plan(n_pre, q, cfg, (int32_t)((n_pre + 15) / 16));
     const int64_t cap = std::min<int64_t>(
-        std::max<int64_t>(q * std::max<int64_t>(1024, 64 * (int64_t)p.n_chunks), 1 << 16),
+        std::max<int64_t>(q * std::max<int64_t>(256, 16 * (int64_t)p.n_chunks), 1 << 16),
         (int64_t)1 << 26);
 
     size_t bytes = 0;
     auto add = [&](size_t count, size_t sz) { bytes += (count * sz + 255) & ~size_t(255); };
     add(p.q_pad, sizeof(QNorm));
     add((size_t)p.n_chunks * p.q_pad, 4);
+    add(p.q_pad, 4);
+    add(p.q_pad, 4);
     add(p.q_pad, 4);
     add(q, 8);
     add(q, 4);
@@ -1003,7 +910,8 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     add(q, 4);
     add(q, 4);
     add(4, 8);
-    add(2 * kXcds, 4);
+    add(kWorkWords, 4);
+    add(p.n_items + pp.n_items, 4);
     add(cap, sizeof(int2));
     add(cap, 4);
     add(cap, 8);
@@ -1012,6 +920,8 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     if (rc) return rc;
     QNorm *qn = ar->take<QNorm>(p.q_pad);
     float *part_val = ar->take<float>((size_t)p.n_chunks * p.q_pad);
+    float *pre_val = ar->take<float>(p.q_pad);
+    int32_t *pre_idx = ar->take<int32_t>(p.q_pad);
     float *win_scan = ar->take<float>(p.q_pad);
     double *win = ar->take<double>(q);
     float *thr = ar->take<float>(q);
@@ -1021,7 +931,8 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     int32_t *qflag = ar->take<int32_t>(q);
     unsigned long long *counter = ar->take<unsigned long long>(4);
     unsigned long long *mu_key = counter + 1;
-    unsigned *work = ar->take<unsigned>(2 * kXcds);
+    unsigned *work = ar->take<unsigned>(kWorkWords);
+    int *redo = ar->take<int>(p.n_items + pp.n_items);
     int2 *pairs = ar->take<int2>(cap);
     float *pair_val = ar->take<float>(cap);
     double *psim = ar->take<double>(cap);
@@ -1045,22 +956,39 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     A.x_stride = kDim;
     A.qs = queries;
     A.q_stride = kDim;
+    A.q_count = (int32_t)q;
+    A.q_pad = (int32_t)p.q_pad;
+    A.qflag = qflag;
+    // prefix pass: largest scan score over the first n_pre rows per query
+    A.n = n_pre;
+    A.n_blocks = (int32_t)((n_pre + 15) / 16);
+    A.chunk_blocks = pp.chunk_blocks;
+    A.n_chunks = pp.n_chunks;
+    A.n_qb = pp.n_qb;
+    A.n_items = pp.n_items;
+    A.part_val = pre_val;
+    A.part_idx = pre_idx;
+    A.redo = redo + p.n_items;
+    A.redo_count = work + 2 * kXcds;
+    rc = launch_scan<kArgmax>(HN_PREC_FP32, kDim, cfg, pp, A, s);
+    if (rc) return rc;
+    // main pass over all rows
     A.n = n;
     A.n_blocks = (int32_t)((n + 15) / 16);
     A.chunk_blocks = p.chunk_blocks;
     A.n_chunks = p.n_chunks;
     A.n_qb = p.n_qb;
     A.n_items = p.n_items;
-    A.q_count = (int32_t)q;
-    A.q_pad = (int32_t)p.q_pad;
     A.part_val = part_val;
+    A.part_idx = nullptr;
     A.thr = win_scan;
+    A.init_best = pre_val;
     A.pairs = pairs;
     A.pair_val = pair_val;
     A.counter = counter;
     A.cap = cap;
-    A.qflag = qflag;
-    A.work = work;
+    A.redo = redo;
+    A.redo_count = work + 2 * kXcds + 1;
     rc = launch_scan<kWindow>(HN_PREC_FP32, kDim, cfg, p, A, s);
     if (rc) return rc;
     {
