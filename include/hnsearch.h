@@ -61,8 +61,11 @@ enum {
 typedef struct {
     int32_t precision;    /* HN_PREC_*; FP32 by default */
     int32_t seed;         /* HN_SEED_*; plain by default */
-    int32_t query_tiles;  /* 16-query MFMA tiles per wave; 0 = tuned */
-    int32_t chunk_blocks; /* 16-entry blocks per work-group; 0 = tuned */
+    int32_t query_tiles;  /* MFMA query tiles per wave (16 or 32 queries each,
+                             by K and precision); 0 = tuned; values the build
+                             does not compile fall to the largest smaller one */
+    int32_t chunk_blocks; /* entry blocks (16 or 32 entries) per work item;
+                             0 = tuned */
     int64_t survivor_cap; /* capacity of the survivor list in (query, entry)
                              pairs; 0 = automatic.  Queries whose survivors
                              do not fit are finished by an exact fallback. */

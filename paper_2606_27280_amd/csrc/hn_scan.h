@@ -1,19 +1,19 @@
 // Major-prefix scan kernels (the hot loop of Algorithm 1's Phase 1 and of
 // its bound test), written for CDNA4 MFMA.
 //
-// Tile: one wave computes a 16-entry x 16-query block of scan scores with
-// MFMA, entries as the A operand (rows) and queries as the B operand
-// (columns).  Lane l holds scores for query l % 16 and entries 4 (l / 16) +
-// v, v = 0..3.  The K dimension is split across the four 16-lane groups: lane
-// group g reads a contiguous slice of each entry row, so a 16-entry block of
-// a [n][W] stream is one contiguous 16 * W element read per wave.  The dot
-// product is a sum over k and the same k -> (step, lane group) bijection is
-// applied to both operands, so any contiguous slicing gives the same set of
-// products; their summation order inside the MFMA is covered by the scan's
-// rounding slack, never relied upon.
+// Tile: one wave computes an R-entry x C-query block of scan scores with one
+// MFMA shape, entries as the A operand (rows) and queries as the B operand
+// (columns).  Two shapes are used: 16x16 (R = C = 16, 4 scores per lane, the
+// K dimension split over four 16-lane groups) and 32x32 (R = C = 32, 16 scores
+// per lane, K split over two 32-lane groups).  Lane group g reads a contiguous
+// slice of each entry row, so an R-entry block of a [n][W] stream is one
+// contiguous R * W element read per wave.  The dot product is a sum over k and
+// the same k -> (step, lane group) bijection is applied to both operands, so
+// any contiguous slicing gives the same set of products; their summation order
+// inside the MFMA is covered by the scan's rounding slack, never relied upon.
 //
 // Work decomposition: a work-group of 4 waves owns one query block (WQ query
-// sub-blocks of NQ 16-query tiles) and one chunk of entry blocks; the 4 / WQ
+// sub-blocks of NQ C-query tiles) and one chunk of entry blocks; the 4 / WQ
 // waves that share a sub-block interleave over the chunk's entry blocks.
 // Work items (query block, chunk) are numbered chunk-major and split into 8
 // contiguous ranges, one per XCD (blockIdx % 8), so the work-groups of one XCD
@@ -28,6 +28,7 @@
 namespace hn {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
@@ -39,12 +40,12 @@ struct ScanArgs {
     const void *qs;     // query operands, row stride q_stride elements
     int64_t q_stride;
     int64_t n;          // valid entries
-    int32_t n_blocks;   // ceil(n / 16)
+    int32_t n_blocks;   // ceil(n / R)
     int32_t chunk_blocks, n_chunks;
     int32_t n_qb, n_items;
     int32_t q_count, q_pad;
     float *part_val;    // argmax / window: [n_chunks][q_pad]
-    int32_t *part_idx;  // argmax: smallest entry of the winning 4-entry group
+    int32_t *part_idx;  // argmax: winning lane group, block * G + g
     const float *thr;   // filter: T_q; window: window width; [q_pad]
     int2 *pairs;        // filter / window: (query, entry)
     float *pair_val;    // window: scan score of the pair
@@ -57,84 +58,138 @@ struct ScanArgs {
     const float *init_best;  // window: starting running maximum per query, or NULL
 };
 
-// ------------------------------------------------------------ operand policies
+// ------------------------------------------------------------ tile shapes
 
-template <int W>  // float32 stream of width W (multiple of 4)
-struct F32Tile {
-    static constexpr int kSlice = W / 4;  // elements per lane group
-    typedef float Elem;
-    struct Frag {
-        float v[kSlice];
-    };
-    __device__ __forceinline__ static void load(Frag &f, const float *p) {
-        if constexpr (kSlice == 1) {
-            f.v[0] = p[0];
-        } else if constexpr (kSlice == 2) {
-            float2 a = *reinterpret_cast<const float2 *>(p);
-            f.v[0] = a.x;
-            f.v[1] = a.y;
+// 16x16 output: lane l holds column l % 16 and rows 4 (l / 16) + v.
+struct Shape16 {
+    static constexpr int kRows = 16, kCols = 16, kGroups = 4, kAcc = 4;
+    typedef v4f Acc;
+    __device__ __forceinline__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+// 32x32 output: lane l holds column l % 32 and rows 8 (v / 4) + 4 (l / 32) + v % 4.
+struct Shape32 {
+    static constexpr int kRows = 32, kCols = 32, kGroups = 2, kAcc = 16;
+    typedef v16f Acc;
+    __device__ __forceinline__ static int out_row(int lane, int v) {
+        return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    }
+};
+
+template <int N>
+struct Regs {  // N consecutive 32-bit values, loaded with the widest loads
+    uint32_t v[N];
+    __device__ __forceinline__ void load(const void *p) {
+        if constexpr (N == 1) {
+            v[0] = *reinterpret_cast<const uint32_t *>(p);
+        } else if constexpr (N == 2) {
+            uint2 a = *reinterpret_cast<const uint2 *>(p);
+            v[0] = a.x;
+            v[1] = a.y;
         } else {
 #pragma unroll
-            for (int c = 0; c < kSlice / 4; ++c) {
-                float4 a = reinterpret_cast<const float4 *>(p)[c];
-                f.v[4 * c + 0] = a.x;
-                f.v[4 * c + 1] = a.y;
-                f.v[4 * c + 2] = a.z;
-                f.v[4 * c + 3] = a.w;
+            for (int c = 0; c < N / 4; ++c) {
+                uint4 a = reinterpret_cast<const uint4 *>(p)[c];
+                v[4 * c + 0] = a.x;
+                v[4 * c + 1] = a.y;
+                v[4 * c + 2] = a.z;
+                v[4 * c + 3] = a.w;
             }
         }
     }
-    __device__ __forceinline__ static void zero(Frag &f) {
+    __device__ __forceinline__ void zero() {
 #pragma unroll
-        for (int m = 0; m < kSlice; ++m) f.v[m] = 0.0f;
+        for (int i = 0; i < N; ++i) v[i] = 0u;
     }
-    __device__ __forceinline__ static v4f mma(const Frag &x, const Frag &q, v4f acc) {
+};
+
+// float32 stream of width W on 16x16x4 MFMA (4 lane groups, W/4 each).
+template <int W>
+struct F32Tile : Shape16 {
+    typedef float Elem;
+    static constexpr int kSlice = W / 4;        // elements per lane group
+    static constexpr int kFragRegs = kSlice;
+    typedef Regs<kFragRegs> Frag;
+    __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
+        Acc acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int m = 0; m < kSlice; ++m)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.v[m], q.v[m], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(x.v[m]),
+                                                       __uint_as_float(q.v[m]), acc, 0, 0, 0);
         return acc;
     }
 };
 
-template <int W>  // bfloat16 stream of width W (16, 32, 64 or 128)
-struct BF16Tile {
-    static constexpr int kSlice = W / 4;
+// float32 stream of width W on 32x32x2 MFMA (2 lane groups, W/2 each).
+template <int W>
+struct F32Tile32 : Shape32 {
+    typedef float Elem;
+    static constexpr int kSlice = W / 2;
+    static constexpr int kFragRegs = kSlice;
+    typedef Regs<kFragRegs> Frag;
+    __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
+        Acc acc = {};
+#pragma unroll
+        for (int m = 0; m < kSlice; ++m)
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(x.v[m]),
+                                                       __uint_as_float(q.v[m]), acc, 0, 0, 0);
+        return acc;
+    }
+};
+
+// bfloat16 stream of width W on 16x16 MFMA: 16x16x16 for W = 16 (4 values per
+// lane group), 16x16x32 steps of 8 values above.
+template <int W>
+struct BF16Tile : Shape16 {
     typedef uint16_t Elem;
-    struct Frag {
-        uint4 v[(kSlice + 7) / 8];  // kSlice = 4 uses the low half of v[0]
-    };
-    __device__ __forceinline__ static void load(Frag &f, const uint16_t *p) {
-        if constexpr (kSlice == 4) {
-            uint2 a = *reinterpret_cast<const uint2 *>(p);
-            f.v[0] = make_uint4(a.x, a.y, 0u, 0u);
-        } else {
-#pragma unroll
-            for (int c = 0; c < kSlice / 8; ++c) f.v[c] = reinterpret_cast<const uint4 *>(p)[c];
-        }
-    }
-    __device__ __forceinline__ static void zero(Frag &f) {
-#pragma unroll
-        for (int c = 0; c < (kSlice + 7) / 8; ++c) f.v[c] = make_uint4(0u, 0u, 0u, 0u);
-    }
-    __device__ __forceinline__ static v4f mma(const Frag &x, const Frag &q, v4f acc) {
+    static constexpr int kSlice = W / 4;
+    static constexpr int kFragRegs = kSlice / 2;
+    typedef Regs<kFragRegs> Frag;
+    __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
+        Acc acc = {0.0f, 0.0f, 0.0f, 0.0f};
         if constexpr (kSlice == 4) {
             v4s a, b;
-            uint2 xa = make_uint2(x.v[0].x, x.v[0].y), qa = make_uint2(q.v[0].x, q.v[0].y);
-            __builtin_memcpy(&a, &xa, 8);
-            __builtin_memcpy(&b, &qa, 8);
-            return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+            __builtin_memcpy(&a, x.v, 8);
+            __builtin_memcpy(&b, q.v, 8);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
         } else {
 #pragma unroll
             for (int c = 0; c < kSlice / 8; ++c) {
                 v8bf a, b;
-                __builtin_memcpy(&a, &x.v[c], 16);
-                __builtin_memcpy(&b, &q.v[c], 16);
+                __builtin_memcpy(&a, x.v + 4 * c, 16);
+                __builtin_memcpy(&b, q.v + 4 * c, 16);
                 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
             }
-            return acc;
         }
+        return acc;
     }
 };
+
+// bfloat16 stream of width W on 32x32x16 MFMA (2 lane groups, W/2 values
+// each, in steps of 8).
+template <int W>
+struct BF16Tile32 : Shape32 {
+    typedef uint16_t Elem;
+    static constexpr int kSlice = W / 2;
+    static constexpr int kFragRegs = kSlice / 2;
+    typedef Regs<kFragRegs> Frag;
+    __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
+        Acc acc = {};
+#pragma unroll
+        for (int c = 0; c < kSlice / 8; ++c) {
+            v8bf a, b;
+            __builtin_memcpy(&a, x.v + 4 * c, 16);
+            __builtin_memcpy(&b, q.v + 4 * c, 16);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        return acc;
+    }
+};
+
+// Registers one tile of a configuration holds per lane (scores + query
+// operand); a configuration is compiled when NQ times this stays within budget.
+template <class Tile>
+constexpr int tile_cost() { return Tile::kAcc + Tile::kFragRegs; }
+constexpr int kTileBudget = 96;
 
 // ------------------------------------------------------------ helpers
 
@@ -143,13 +198,21 @@ __device__ __forceinline__ unsigned lane_prefix(unsigned long long m) {
                                      __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
+template <class Acc, int N>
+__device__ __forceinline__ float acc_max(const Acc &a) {
+    float m = a[0];
+#pragma unroll
+    for (int v = 1; v < N; ++v) m = fmaxf(m, a[v]);
+    return m;
+}
+
 // Survivor staging.  In the hot loop each wave appends (query, entry) pairs to
 // its own LDS buffer only, so the loop issues no global stores (which would
-// make the compiler drain the prefetch ring); the buffer is flushed to the
+// make the compiler drain the loads in flight); the buffer is flushed to the
 // global list with one atomic per wave at the end of the work item.  A wave
 // whose buffer fills marks the item for a re-run by scan_redo_kernel, which
-// flushes whenever its buffer fills (DIRECT); the set of pairs is the same.
-constexpr int kEmitCap = 512;  // pairs per wave buffer (>= 64 lanes x 4 entries)
+// flushes whenever its buffer fills (Direct); the set of pairs is the same.
+constexpr int kEmitCap = 512;  // pairs per wave buffer (>= 64 lanes x 4 slots)
 
 struct EmitBuf {
     int2 *pairs;  // LDS [kEmitCap]
@@ -179,38 +242,47 @@ __device__ __forceinline__ void flush_pairs(const ScanArgs &A, EmitBuf &B) {
     B.count = 0;
 }
 
-// Append the lane's entries with score >= t: ballot per entry slot, positions
-// by popcount + mbcnt prefix counts.
-template <bool WithVal, bool Direct>
-__device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B, v4f a, float t,
-                                           bool qvalid, int q, int e0) {
-    bool p0 = qvalid && a[0] >= t, p1 = qvalid && a[1] >= t;
-    bool p2 = qvalid && a[2] >= t, p3 = qvalid && a[3] >= t;
-    unsigned long long m0 = __ballot(p0), m1 = __ballot(p1), m2 = __ballot(p2),
-                       m3 = __ballot(p3);
-    const int c0 = __popcll(m0), c1 = __popcll(m1), c2 = __popcll(m2), c3 = __popcll(m3);
-    const int total = c0 + c1 + c2 + c3;
-    if (total == 0) return;
-    if (B.count + total > kEmitCap) {
-        if constexpr (Direct) {
-            flush_pairs<WithVal>(A, B);
-        } else {
-            B.full = true;
-            return;
-        }
-    }
-    const bool pv[4] = {p0, p1, p2, p3};
-    const unsigned long long mv[4] = {m0, m1, m2, m3};
-    const int off[4] = {0, c0, c0 + c1, c0 + c1 + c2};
+// Append the lane's entries with score >= t, in groups of 4 accumulator
+// slots: ballot per slot, positions by popcount + mbcnt prefix counts.
+template <class Tile, bool WithVal, bool Direct>
+__device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B,
+                                           const typename Tile::Acc &a, float t, bool qvalid,
+                                           int q, int eblk) {
+    const int lane = (int)__lane_id();
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        if (pv[v]) {
-            const int pos = B.count + off[v] + (int)lane_prefix(mv[v]);
-            B.pairs[pos] = make_int2(q, e0 + v);
-            if (WithVal) B.vals[pos] = a[v];
+    for (int v0 = 0; v0 < Tile::kAcc; v0 += 4) {
+        bool pv[4];
+        unsigned long long mv[4];
+        int c[4];
+        int total = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pv[u] = qvalid && a[v0 + u] >= t;
+            mv[u] = __ballot(pv[u]);
+            c[u] = __popcll(mv[u]);
+            total += c[u];
         }
+        if (total == 0) continue;
+        if (B.count + total > kEmitCap) {
+            if constexpr (Direct) {
+                flush_pairs<WithVal>(A, B);
+            } else {
+                B.full = true;
+                return;
+            }
+        }
+        int off = B.count;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (pv[u]) {
+                const int pos = off + (int)lane_prefix(mv[u]);
+                B.pairs[pos] = make_int2(q, eblk + Tile::out_row(lane, v0 + u));
+                if (WithVal) B.vals[pos] = a[v0 + u];
+            }
+            off += c[u];
+        }
+        B.count += total;
     }
-    B.count += total;
 }
 
 // Lexicographic (value desc, index asc) merge; idx < 0 marks "none".
@@ -226,15 +298,18 @@ __device__ __forceinline__ void lex_merge(float &v, int &i, float ov, int oi) {
 // One work item: query block qb x entry chunk `chunk`.
 template <class Tile, int NQ, int WQ, int MODE, bool Direct>
 __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
-                                          float (*sh_val)[NQ * 16], int (*sh_idx)[NQ * 16],
-                                          int *sh_full, EmitBuf &eb) {
+                                          float (*sh_val)[NQ * Tile::kCols],
+                                          int (*sh_idx)[NQ * Tile::kCols], int *sh_full,
+                                          EmitBuf &eb) {
     typedef typename Tile::Elem Elem;
     typedef typename Tile::Frag Frag;
+    typedef typename Tile::Acc Acc;
+    constexpr int R = Tile::kRows, C = Tile::kCols, G = Tile::kGroups, NA = Tile::kAcc;
     constexpr int NS = kWaves / WQ;  // waves sharing one query sub-block
     const int chunk = item / A.n_qb, qb = item % A.n_qb;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int g = lane >> 4, r = lane & 15;
+    const int g = lane / R, r = lane % R;  // lane group (K slice) and row / column
     const int wq = wave % WQ, ws = wave / WQ;
     const int tile0 = (qb * WQ + wq) * NQ;
 
@@ -246,11 +321,11 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
     int bblk[NQ];
 #pragma unroll
     for (int t = 0; t < NQ; ++t) {
-        qid[t] = (tile0 + t) * 16 + r;
+        qid[t] = (tile0 + t) * C + r;
         if (qid[t] < A.q_count)
-            Tile::load(qf[t], qsrc + (int64_t)qid[t] * A.q_stride + g * Tile::kSlice);
+            qf[t].load(qsrc + (int64_t)qid[t] * A.q_stride + g * Tile::kSlice);
         else
-            Tile::zero(qf[t]);
+            qf[t].zero();
         thr[t] = (MODE == kFilter || MODE == kWindow) ? A.thr[qid[t]] : 0.0f;
         best[t] = (MODE == kWindow && A.init_best) ? A.init_best[qid[t]] : -INFINITY;
         bblk[t] = -1;
@@ -264,14 +339,13 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
     // computed the other one is loading.  Every slot is loaded on every step
     // (past the item's end the address is clamped to its last block), so the
     // loads in flight at any point are a fixed, whole group.
-    constexpr int kFragRegs = Tile::kSlice * (int)sizeof(Elem) / 4;
-    constexpr int PF = kFragRegs <= 2 ? 8 : (kFragRegs <= 4 ? 4 : 1);
+    constexpr int PF = Tile::kFragRegs <= 2 ? 8 : (Tile::kFragRegs <= 4 ? 4 : 1);
     const int blk_last = max(blk1 - 1, 0);
     auto load_group = [&](Frag (&xg)[PF], int gbase) {
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
             const int b = min(gbase + j * NS, blk_last);
-            Tile::load(xg[j], xcol + min((int64_t)b * 16 + r, last_row) * A.x_stride);
+            xg[j].load(xcol + min((int64_t)b * R + r, last_row) * A.x_stride);
         }
     };
     auto compute_group = [&](const Frag (&xg)[PF], int gbase) {
@@ -279,24 +353,20 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
         for (int j = 0; j < PF; ++j) {
             const int blk = gbase + j * NS;
             if (blk >= blk1) break;
-            v4f acc[NQ];
+            Acc acc[NQ];
 #pragma unroll
-            for (int t = 0; t < NQ; ++t) {
-                const v4f z = {0.0f, 0.0f, 0.0f, 0.0f};
-                acc[t] = Tile::mma(xg[j], qf[t], z);
-            }
-            const int e0 = blk * 16 + 4 * g;
-            if ((int64_t)(blk + 1) * 16 > A.n) {
+            for (int t = 0; t < NQ; ++t) acc[t] = Tile::mma(xg[j], qf[t]);
+            const int eblk = blk * R;
+            if ((int64_t)eblk + R > A.n) {
 #pragma unroll
                 for (int t = 0; t < NQ; ++t)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        if (e0 + v >= A.n) acc[t][v] = -INFINITY;
+                    for (int v = 0; v < NA; ++v)
+                        if (eblk + Tile::out_row(lane, v) >= A.n) acc[t][v] = -INFINITY;
             }
             float mx[NQ];
 #pragma unroll
-            for (int t = 0; t < NQ; ++t)
-                mx[t] = fmaxf(fmaxf(acc[t][0], acc[t][1]), fmaxf(acc[t][2], acc[t][3]));
+            for (int t = 0; t < NQ; ++t) mx[t] = acc_max<Acc, NA>(acc[t]);
             if constexpr (MODE == kArgmax) {
 #pragma unroll
                 for (int t = 0; t < NQ; ++t) {
@@ -313,8 +383,8 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
 #pragma unroll
                     for (int t = 0; t < NQ; ++t)
                         if (__ballot(mx[t] >= thr[t]))
-                            emit_pairs<false, Direct>(A, eb, acc[t], thr[t], qid[t] < A.q_count,
-                                                      qid[t], e0);
+                            emit_pairs<Tile, false, Direct>(A, eb, acc[t], thr[t],
+                                                            qid[t] < A.q_count, qid[t], eblk);
                 }
             } else if constexpr (MODE == kWindow) {
                 float lim[NQ];
@@ -329,16 +399,18 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
 #pragma unroll
                     for (int t = 0; t < NQ; ++t)
                         if (__ballot(mx[t] >= lim[t]))
-                            emit_pairs<true, Direct>(A, eb, acc[t], lim[t], qid[t] < A.q_count,
-                                                     qid[t], e0);
+                            emit_pairs<Tile, true, Direct>(A, eb, acc[t], lim[t],
+                                                           qid[t] < A.q_count, qid[t], eblk);
                 }
             } else {
 #pragma unroll
                 for (int t = 0; t < NQ; ++t) {
                     if (qid[t] < A.q_count) {
 #pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            if (e0 + v < A.n) A.scores[(int64_t)qid[t] * A.n + e0 + v] = acc[t][v];
+                        for (int v = 0; v < NA; ++v) {
+                            const int e = eblk + Tile::out_row(lane, v);
+                            if (e < A.n) A.scores[(int64_t)qid[t] * A.n + e] = acc[t][v];
+                        }
                     }
                 }
             }
@@ -360,6 +432,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
         compute_group(xb, base + kStep);
         __builtin_amdgcn_sched_barrier(0);
     }
+
     if constexpr (MODE == kFilter || MODE == kWindow) {
         if constexpr (Direct) {
             flush_pairs<MODE == kWindow>(A, eb);
@@ -383,32 +456,33 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
     }
 
     if constexpr (MODE == kArgmax || MODE == kWindow) {
-        // per query: merge the 4 lane groups, then the NS waves of the sub-block
+        // per query: merge the lane groups, then the NS waves of the sub-block.
+        // The argmax index is the winning lane group, block * G + g.
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
             float v = best[t];
-            int i = (MODE == kArgmax) ? (bblk[t] >= 0 ? bblk[t] * 16 + 4 * g : -1)
+            int i = (MODE == kArgmax) ? (bblk[t] >= 0 ? bblk[t] * G + g : -1)
                                       : (v > -INFINITY ? 0 : -1);
 #pragma unroll
-            for (int o = 16; o < 64; o <<= 1) {
+            for (int o = R; o < 64; o <<= 1) {
                 float ov = __shfl_xor(v, o);
                 int oi = __shfl_xor(i, o);
                 lex_merge(v, i, ov, oi);
             }
             if (g == 0) {
-                sh_val[wave][t * 16 + r] = v;
-                sh_idx[wave][t * 16 + r] = i;
+                sh_val[wave][t * C + r] = v;
+                sh_idx[wave][t * C + r] = i;
             }
         }
         __syncthreads();
         if (ws == 0 && g == 0) {
 #pragma unroll
             for (int t = 0; t < NQ; ++t) {
-                float v = sh_val[wave][t * 16 + r];
-                int i = sh_idx[wave][t * 16 + r];
+                float v = sh_val[wave][t * C + r];
+                int i = sh_idx[wave][t * C + r];
                 for (int s = 1; s < NS; ++s)
-                    lex_merge(v, i, sh_val[wave + s * WQ][t * 16 + r],
-                              sh_idx[wave + s * WQ][t * 16 + r]);
+                    lex_merge(v, i, sh_val[wave + s * WQ][t * C + r],
+                              sh_idx[wave + s * WQ][t * C + r]);
                 const int q = qid[t];
                 if (q < A.q_pad) {
                     A.part_val[(int64_t)chunk * A.q_pad + q] = v;
@@ -419,9 +493,9 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
     }
 }
 
-#define HN_SCAN_SHARED(NQ, MODE)                                                          \
-    __shared__ float sh_val[kWaves][NQ * 16];                                             \
-    __shared__ int sh_idx[kWaves][NQ * 16];                                               \
+#define HN_SCAN_SHARED(Tile, NQ, MODE)                                                    \
+    __shared__ float sh_val[kWaves][NQ * Tile::kCols];                                    \
+    __shared__ int sh_idx[kWaves][NQ * Tile::kCols];                                      \
     __shared__ int sh_full[kWaves];                                                       \
     constexpr bool kEmits = MODE == kFilter || MODE == kWindow;                           \
     __shared__ int2 sh_pairs[kEmits ? kWaves : 1][kEmits ? kEmitCap : 1];                 \
@@ -441,7 +515,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
 // times.
 template <class Tile, int NQ, int WQ, int MODE>
 __global__ __launch_bounds__(256) void scan_kernel(ScanArgs A) {
-    HN_SCAN_SHARED(NQ, MODE)
+    HN_SCAN_SHARED(Tile, NQ, MODE)
     const int groups_per_xcd = (int)gridDim.x / kXcds;
     const int x = (int)(blockIdx.x % kXcds), w = (int)(blockIdx.x / kXcds);
     const int per = (A.n_items + kXcds - 1) / kXcds;
@@ -453,51 +527,73 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs A) {
 // Re-runs the items whose survivor buffers overflowed, flushing as it goes.
 template <class Tile, int NQ, int WQ, int MODE>
 __global__ __launch_bounds__(256) void scan_redo_kernel(ScanArgs A) {
-    HN_SCAN_SHARED(NQ, MODE)
+    HN_SCAN_SHARED(Tile, NQ, MODE)
     const unsigned n = __builtin_amdgcn_readfirstlane(*A.redo_count);
     for (unsigned r = blockIdx.x; r < n; r += gridDim.x)
         scan_item<Tile, NQ, WQ, MODE, true>(A, __builtin_amdgcn_readfirstlane(A.redo[r]), sh_val,
                                             sh_idx, sh_full, eb);
 }
 
+// ------------------------------------------------------------ host side
+
+// Shape of a launch: query tiles per wave (NQ) x query sub-blocks per group
+// (WQ), tile width C, entries per block R.
 struct Plan {
-    int nq = 4, wq = 4;  // 16-query tiles per wave, query sub-blocks per group
-    int qb_size() const { return nq * wq * 16; }
-    int32_t n_qb = 0, chunk_blocks = 0, n_chunks = 0, n_items = 0;
+    int nq = 4, wq = 4, cols = 16, rows = 16;
+    int qb_size() const { return nq * wq * cols; }
+    int32_t n_qb = 0, n_blocks = 0, chunk_blocks = 0, n_chunks = 0, n_items = 0;
     int64_t q_pad = 0;
 };
 
-// Configurations compiled for each operand policy: (NQ, WQ).
+// Configurations compiled for each tile: (NQ, WQ).
 constexpr int kNumCfg = 6;
 constexpr int kCfgNQ[kNumCfg] = {1, 2, 4, 2, 4, 8};
 constexpr int kCfgWQ[kNumCfg] = {1, 1, 1, 4, 4, 4};
 
-inline int pick_cfg(int64_t q, int slice_regs, int forced_nq) {
-    int best = 0;
+// Smallest configuration whose query block covers q (largest if none),
+// within the register budget.  forced_nq > 0 restricts NQ to the largest
+// compiled value not above it.  -1 if none fits.
+inline int pick_cfg(int64_t q, int cols, int cost, int forced_nq) {
+    if (forced_nq > 0) {
+        int nq = 0;
+        for (int c = 0; c < kNumCfg; ++c)
+            if (kCfgNQ[c] * cost <= kTileBudget && kCfgNQ[c] <= forced_nq && kCfgNQ[c] > nq)
+                nq = kCfgNQ[c];
+        forced_nq = nq;
+        if (nq == 0) return -1;
+    }
+    // Unforced, the 32x32 shape keeps at most 2 tiles per wave: its 16
+    // scores per tile make larger NQ cost occupancy (measured: NQ = 2 beats 4).
+    const int auto_cap = cols == 32 ? 2 : 8;
+    int best = -1;
     for (int c = 0; c < kNumCfg; ++c) {
-        if (kCfgNQ[c] * slice_regs > 64) continue;
+        if (kCfgNQ[c] * cost > kTileBudget) continue;
         if (forced_nq > 0 && kCfgNQ[c] != forced_nq) continue;
+        if (forced_nq <= 0 && kCfgNQ[c] > auto_cap) continue;
         best = c;
-        if ((int64_t)kCfgNQ[c] * kCfgWQ[c] * 16 >= q) break;
+        if ((int64_t)kCfgNQ[c] * kCfgWQ[c] * cols >= q) break;
     }
     return best;
 }
 
-inline Plan make_plan(int64_t n, int64_t q, int cfg, int chunk_blocks) {
+inline Plan make_plan(int64_t n, int64_t q, int cfg, int chunk_blocks, int rows, int cols,
+                      int64_t target_items = 8192) {
     Plan p;
     p.nq = kCfgNQ[cfg];
     p.wq = kCfgWQ[cfg];
+    p.rows = rows;
+    p.cols = cols;
     const int64_t qb = p.qb_size();
     p.n_qb = (int32_t)((q + qb - 1) / qb);
     p.q_pad = (int64_t)p.n_qb * qb;
-    const int32_t n_blocks = (int32_t)((n + 15) / 16);
+    p.n_blocks = (int32_t)((n + rows - 1) / rows);
     if (chunk_blocks <= 0) {
-        const int64_t target_items = 16384;
         int64_t want_chunks = std::max<int64_t>(1, (target_items + p.n_qb - 1) / p.n_qb);
-        chunk_blocks = (int32_t)std::max<int64_t>(8, (n_blocks + want_chunks - 1) / want_chunks);
+        chunk_blocks =
+            (int32_t)std::max<int64_t>(8, (p.n_blocks + want_chunks - 1) / want_chunks);
     }
-    p.chunk_blocks = std::min<int32_t>(chunk_blocks, n_blocks);
-    p.n_chunks = (n_blocks + p.chunk_blocks - 1) / p.chunk_blocks;
+    p.chunk_blocks = std::min<int32_t>(chunk_blocks, p.n_blocks);
+    p.n_chunks = (p.n_blocks + p.chunk_blocks - 1) / p.chunk_blocks;
     p.n_items = p.n_qb * p.n_chunks;
     return p;
 }
@@ -539,7 +635,7 @@ inline unsigned persistent_grid(int n_items) {
 
 template <class Tile, int MODE, int C>
 inline void launch_one(const Plan &p, const ScanArgs &A, hipStream_t s) {
-    if constexpr (kCfgNQ[C] * Tile::kSlice * sizeof(typename Tile::Elem) / 4 <= 64) {
+    if constexpr (kCfgNQ[C] * tile_cost<Tile>() <= kTileBudget) {
         hipLaunchKernelGGL((scan_kernel<Tile, kCfgNQ[C], kCfgWQ[C], MODE>),
                            dim3(persistent_grid<Tile, kCfgNQ[C], kCfgWQ[C], MODE>(p.n_items)),
                            dim3(256), 0, s, A);
@@ -567,6 +663,7 @@ inline void launch_cfgs(int cfg, const Plan &p, const ScanArgs &A, hipStream_t s
 // requested combination is not compiled.
 template <class Tile, bool Window>
 inline int launch_tile(int mode, int cfg, const Plan &p, const ScanArgs &A, hipStream_t s) {
+    if (cfg < 0 || cfg >= kNumCfg || kCfgNQ[cfg] * tile_cost<Tile>() > kTileBudget) return 1;
     switch (mode) {
         case kArgmax: launch_cfgs<Tile, kArgmax>(cfg, p, A, s); return 0;
         case kFilter: launch_cfgs<Tile, kFilter>(cfg, p, A, s); return 0;
@@ -584,12 +681,26 @@ inline int launch_tile(int mode, int cfg, const Plan &p, const ScanArgs &A, hipS
     return 1;
 }
 
+// Tile families: for each precision, a stream of width W up to 32 runs on the
+// 32x32 shape, wider streams on the 16x16 shape.  cost = tile_cost<Tile>().
+struct TileInfo {
+    int rows, cols, cost, groups;
+};
+inline TileInfo tile_info(int precision, int w) {
+    if (precision == HN_PREC_FP32) {
+        if (w <= 32) return TileInfo{32, 32, 16 + w / 2, 2};
+        return TileInfo{16, 16, 4 + w / 4, 4};
+    }
+    if (w <= 32) return TileInfo{32, 32, 16 + w / 4, 2};
+    return TileInfo{16, 16, 4 + w / 8, 4};
+}
+
 // Per-precision launchers, each compiled in its own translation unit.
 int launch_scan_f32_narrow(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
-                           hipStream_t s);  // widths 4, 8, 16
+                           hipStream_t s);  // widths 4, 8, 16, 32 (32x32 tiles)
 int launch_scan_f32_wide(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
-                         hipStream_t s);    // widths 32, 64, 128
+                         hipStream_t s);    // widths 64, 128 (16x16 tiles)
 int launch_scan_bf16(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
-                     hipStream_t s);        // widths 16, 32, 64, 128
+                     hipStream_t s);        // widths 16, 32 (32x32), 64, 128 (16x16)
 
 }  // namespace hn

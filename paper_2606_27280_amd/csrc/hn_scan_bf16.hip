@@ -1,11 +1,12 @@
-// Bfloat16 scan kernels (MFMA 16x16x16 for K <= 16, 16x16x32 steps above).
+// Bfloat16 scan kernels: widths 16 and 32 on the 32x32x16 MFMA shape, widths
+// 64 and 128 on 16x16x32.
 #include "hn_scan.h"
 
 namespace hn {
 int launch_scan_bf16(int mode, int w, int cfg, const Plan &p, const ScanArgs &A, hipStream_t s) {
     switch (w) {
-        case 16: return launch_tile<BF16Tile<16>, false>(mode, cfg, p, A, s);
-        case 32: return launch_tile<BF16Tile<32>, false>(mode, cfg, p, A, s);
+        case 16: return launch_tile<BF16Tile32<16>, false>(mode, cfg, p, A, s);
+        case 32: return launch_tile<BF16Tile32<32>, false>(mode, cfg, p, A, s);
         case 64: return launch_tile<BF16Tile<64>, false>(mode, cfg, p, A, s);
         case 128: return launch_tile<BF16Tile<128>, false>(mode, cfg, p, A, s);
     }

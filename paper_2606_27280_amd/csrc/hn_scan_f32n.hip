@@ -1,13 +1,15 @@
-// Float32 scan kernels, stream widths 4, 8 and 16 (K <= 16).
+// Float32 scan kernels for stream widths 4, 8, 16 and 32 (K <= 32) on the
+// 32x32x2 MFMA shape.
 #include "hn_scan.h"
 
 namespace hn {
 int launch_scan_f32_narrow(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
                            hipStream_t s) {
     switch (w) {
-        case 4: return launch_tile<F32Tile<4>, false>(mode, cfg, p, A, s);
-        case 8: return launch_tile<F32Tile<8>, false>(mode, cfg, p, A, s);
-        case 16: return launch_tile<F32Tile<16>, false>(mode, cfg, p, A, s);
+        case 4: return launch_tile<F32Tile32<4>, false>(mode, cfg, p, A, s);
+        case 8: return launch_tile<F32Tile32<8>, false>(mode, cfg, p, A, s);
+        case 16: return launch_tile<F32Tile32<16>, false>(mode, cfg, p, A, s);
+        case 32: return launch_tile<F32Tile32<32>, false>(mode, cfg, p, A, s);
     }
     return 1;
 }

@@ -90,6 +90,7 @@ struct SeedArgs {
     const float *part_val;
     const int32_t *part_idx;
     int32_t n_chunks, q_pad;
+    int32_t shape, group_size;  // scan tile shape (16 or 32) and entries per lane group
     const float *queries;
     int64_t q;
     const float *rows;
@@ -118,25 +119,39 @@ struct SeedArgs {
 
 __device__ __forceinline__ float round_down_f32(double v) { return __double2float_rd(v); }
 
+// Entry of slot v of an argmax lane group gid = block * G + g, for the scan's
+// tile shape: 16x16 tiles give 4 consecutive entries, 32x32 tiles 16 entries
+// (rows 8 (v / 4) + 4 g + v % 4 of the block).
+__device__ __forceinline__ int64_t group_entry(int shape, int gid, int v) {
+    if (shape == 16) return (int64_t)(gid >> 2) * 16 + 4 * (gid & 3) + v;
+    return (int64_t)(gid >> 1) * 32 + 8 * (v >> 2) + 4 * (gid & 1) + (v & 3);
+}
+
+// One wave per query: reduce the per-chunk argmax partials, rescore every
+// entry of the winning lane group in float64 (one lane each) and keep the
+// best (sim desc, index asc) as the seed; then the slack and thresholds.
 __global__ __launch_bounds__(256) void seed_kernel(SeedArgs S) {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i == 0) *S.counter = 0;
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i == 0 && lane == 0) *S.counter = 0;
     if (i >= S.q_pad) return;
     if (i >= S.q) {
-        S.thr[i] = INFINITY;
+        if (lane == 0) S.thr[i] = INFINITY;
         return;
     }
     const QNorm qn = S.qn[i];
-    S.best_idx[i] = kIdxNone;
-    S.cnt[i] = 0;
-    S.qflag[i] = 0;
     if (qn.bad) {
-        S.thr[i] = INFINITY;
-        if (S.thr32) S.thr32[i] = INFINITY;
-        S.seed_idx[i] = -1;
-        S.seed_sim[i] = NAN;
-        S.slack[i] = NAN;
-        S.best_key[i] = 0;
+        if (lane == 0) {
+            S.best_idx[i] = kIdxNone;
+            S.cnt[i] = 0;
+            S.qflag[i] = 0;
+            S.thr[i] = INFINITY;
+            if (S.thr32) S.thr32[i] = INFINITY;
+            S.seed_idx[i] = -1;
+            S.seed_sim[i] = NAN;
+            S.slack[i] = NAN;
+            S.best_key[i] = 0;
+        }
         return;
     }
     const float *qv = S.queries + i * kDim;
@@ -147,19 +162,38 @@ __global__ __launch_bounds__(256) void seed_kernel(SeedArgs S) {
     } else {
         float bv = -INFINITY;
         int bi = -1;
-        for (int c = 0; c < S.n_chunks; ++c)
+        for (int c = lane; c < S.n_chunks; c += 64)
             lex_merge(bv, bi, S.part_val[(int64_t)c * S.q_pad + i],
                       S.part_idx[(int64_t)c * S.q_pad + i]);
-        // rescore the winning 4-entry group; its best sim is the seed bound
-        L = -INFINITY;
-        for (int e = bi; e >= 0 && e < bi + 4 && e < S.n; ++e) {
-            double s = sim64(qv, S.rows + (int64_t)e * kDim);
-            if (b < 0 || s > L) {
-                L = s;
-                b = e;
+        for (int o = 32; o > 0; o >>= 1) {
+            const float ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o);
+            lex_merge(bv, bi, ov, oi);
+        }
+        double sv = -INFINITY;
+        int64_t e = -1;
+        if (bi >= 0 && lane < S.group_size) {
+            e = group_entry(S.shape, bi, lane);
+            if (e < S.n)
+                sv = sim64(qv, S.rows + e * kDim);
+            else
+                e = -1;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double os = __shfl_xor(sv, o);
+            const int64_t oe = __shfl_xor(e, o);
+            if (oe >= 0 && (e < 0 || os > sv || (os == sv && oe < e))) {
+                sv = os;
+                e = oe;
             }
         }
+        L = sv;
+        b = e;
     }
+    if (lane != 0) return;
+    S.best_idx[i] = kIdxNone;
+    S.cnt[i] = 0;
+    S.qflag[i] = 0;
     // slack: scan rounding + stored-norm excess (Eq. 3) + float64 evaluation
     double es = S.scan_rel * qn.major * S.scan_mu;
     if (S.scan_res) {
@@ -201,6 +235,7 @@ struct RescoreArgs {
     const int64_t *seed_idx;
     const double *seed_sim;
     int64_t q;
+    int count;  // count survivors per query (only when requested)
 };
 
 __device__ __forceinline__ int64_t pair_count(const RescoreArgs &R) {
@@ -216,7 +251,7 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs R) {
          p += (int64_t)gridDim.x * 256) {
         const int2 pr = R.pairs[p];
         const float *qv = R.queries + (int64_t)pr.x * kDim;
-        atomicAdd(&R.cnt[pr.x], 1);
+        if (R.count) atomicAdd(&R.cnt[pr.x], 1);
         bool keep = true;
         if (MODE == 1) {
             const float *xm = R.major32 + (int64_t)pr.y * R.kp;
@@ -449,7 +484,7 @@ int launch_scan(int precision, int w, int cfg, const Plan &p, const ScanArgs &A,
     ProfScope prof(s, scan_tag(MODE, precision));
     int rc;
     if (precision == HN_PREC_FP32)
-        rc = w <= 16 ? launch_scan_f32_narrow(MODE, w, cfg, p, A, s)
+        rc = w <= 32 ? launch_scan_f32_narrow(MODE, w, cfg, p, A, s)
                      : launch_scan_f32_wide(MODE, w, cfg, p, A, s);
     else if (precision == HN_PREC_BF16)
         rc = launch_scan_bf16(MODE, w, cfg, p, A, s);
@@ -460,7 +495,6 @@ int launch_scan(int precision, int w, int cfg, const Plan &p, const ScanArgs &A,
     return HN_OK;
 }
 
-int slice_regs(int precision, int w) { return precision == HN_PREC_FP32 ? w / 4 : w / 8; }
 
 // Everything one search call needs on the device.
 struct Work {
@@ -468,6 +502,7 @@ struct Work {
     int cfg = 0;
     int precision = HN_PREC_FP32;
     int width = 0;
+    int shape = 16;  // tile shape of the scan (16 or 32): decodes argmax groups
     const void *stream_x = nullptr;
     float *op32 = nullptr;
     uint16_t *op16 = nullptr;
@@ -508,8 +543,13 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     W.precision = o.precision;
     W.width = W.precision == HN_PREC_FP32 ? ix->kp : ix->kb;
     W.stream_x = W.precision == HN_PREC_FP32 ? (const void *)ix->major32 : (const void *)ix->major16;
-    W.cfg = pick_cfg(q, slice_regs(W.precision, W.width), o.query_tiles);
-    W.plan = make_plan(ix->n, q, W.cfg, o.chunk_blocks);
+    const TileInfo ti = tile_info(W.precision, W.width);
+    W.cfg = pick_cfg(q, ti.cols, ti.cost, o.query_tiles);
+    if (W.cfg < 0)
+        return fail(HN_ERR_INVALID_ARG, "query_tiles=%d is not available for this width",
+                    o.query_tiles);
+    W.plan = make_plan(ix->n, q, W.cfg, o.chunk_blocks, ti.rows, ti.cols);
+    W.shape = ti.rows;
     const Plan &p = W.plan;
     W.cap = cap;
 
@@ -572,7 +612,7 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     A.qs = W.precision == HN_PREC_FP32 ? (const void *)W.op32 : (const void *)W.op16;
     A.q_stride = W.width;
     A.n = ix->n;
-    A.n_blocks = (int32_t)((ix->n + 15) / 16);
+    A.n_blocks = p.n_blocks;
     A.chunk_blocks = p.chunk_blocks;
     A.n_chunks = p.n_chunks;
     A.n_qb = p.n_qb;
@@ -594,6 +634,8 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     S.part_idx = W.part_idx;
     S.n_chunks = p.n_chunks;
     S.q_pad = (int32_t)p.q_pad;
+    S.shape = W.shape;
+    S.group_size = W.shape == 16 ? 4 : 16;
     S.queries = queries;
     S.q = q;
     S.rows = ix->rows;
@@ -637,7 +679,7 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     S.counter = W.counter;
     {
         ProfScope prof_(s, "seed");
-        hipLaunchKernelGGL(seed_kernel, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, S);
+        hipLaunchKernelGGL(seed_kernel, dim3(blocks_for(p.q_pad, 4)), dim3(256), 0, s, S);
     }
     HN_HIP(hipGetLastError());
     return HN_OK;
@@ -652,7 +694,7 @@ ScanArgs filter_args(const hn_index *ix, const Work &W, int64_t q, int2 *pairs, 
     A.qs = W.precision == HN_PREC_FP32 ? (const void *)W.op32 : (const void *)W.op16;
     A.q_stride = W.width;
     A.n = ix->n;
-    A.n_blocks = (int32_t)((ix->n + 15) / 16);
+    A.n_blocks = p.n_blocks;
     A.chunk_blocks = p.chunk_blocks;
     A.n_chunks = p.n_chunks;
     A.n_qb = p.n_qb;
@@ -722,6 +764,7 @@ extern "C" int hn_search_top1(const hn_index *ix, const float *queries, int64_t 
     R.seed_idx = W.seed_idx;
     R.seed_sim = W.seed_sim;
     R.q = q;
+    R.count = (aux && aux->survivors) || stats;
     const unsigned rgrid = 2048;
     if (W.precision == HN_PREC_FP32) {
         ProfScope prof_(s, "rescore");
@@ -837,7 +880,8 @@ extern "C" int hn_scan_scores(const hn_index *ix, const float *queries, int64_t 
     W.precision = precision;
     W.width = precision == HN_PREC_FP32 ? ix->kp : ix->kb;
     W.cfg = 0;
-    W.plan = make_plan(ix->n, q, W.cfg, 0);
+    const TileInfo ti = tile_info(precision, W.width);
+    W.plan = make_plan(ix->n, q, W.cfg, 0, ti.rows, ti.cols);
     (void)o;
     const Plan &p = W.plan;
     size_t bytes = ((p.q_pad * ix->kp * 4 + 255) & ~size_t(255)) +
@@ -861,7 +905,7 @@ extern "C" int hn_scan_scores(const hn_index *ix, const float *queries, int64_t 
     A.qs = precision == HN_PREC_FP32 ? (const void *)W.op32 : (const void *)W.op16;
     A.q_stride = W.width;
     A.n = ix->n;
-    A.n_blocks = (int32_t)((ix->n + 15) / 16);
+    A.n_blocks = p.n_blocks;
     A.chunk_blocks = p.chunk_blocks;
     A.n_chunks = p.n_chunks;
     A.n_qb = p.n_qb;
@@ -885,13 +929,15 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
         return fail(HN_ERR_INVALID_ARG, "null pointer argument");
     if (q == 0) return HN_OK;
     hipStream_t s = (hipStream_t)stream;
-    const int cfg = pick_cfg(q, kDim / 4, 2);
-    Plan p = make_plan(n, q, cfg, 0);
+    const TileInfo ti = tile_info(HN_PREC_FP32, kDim);
+    const int cfg = pick_cfg(q, ti.cols, ti.cost, 2);
+    Plan p = make_plan(n, q, cfg, 0, ti.rows, ti.cols);
     // A prefix pass (one chunk of the first n_pre rows) gives each query a
     // starting running maximum: a real scan score, so never above the final
     // maximum, and far fewer near-record candidates in the main pass.
     const int64_t n_pre = std::min<int64_t>(n, 4096);
-    Plan pp = make_plan(n_pre, q, cfg, (int32_t)((n_pre + 15) / 16));
+    Plan pp = make_plan(n_pre, q, cfg, (int32_t)((n_pre + ti.rows - 1) / ti.rows), ti.rows,
+                        ti.cols);
     const int64_t cap = std::min<int64_t>(
         std::max<int64_t>(q * std::max<int64_t>(256, 16 * (int64_t)p.n_chunks), 1 << 16),
         (int64_t)1 << 26);
@@ -961,7 +1007,7 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     A.qflag = qflag;
     // prefix pass: largest scan score over the first n_pre rows per query
     A.n = n_pre;
-    A.n_blocks = (int32_t)((n_pre + 15) / 16);
+    A.n_blocks = pp.n_blocks;
     A.chunk_blocks = pp.chunk_blocks;
     A.n_chunks = pp.n_chunks;
     A.n_qb = pp.n_qb;
@@ -974,7 +1020,7 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     if (rc) return rc;
     // main pass over all rows
     A.n = n;
-    A.n_blocks = (int32_t)((n + 15) / 16);
+    A.n_blocks = p.n_blocks;
     A.chunk_blocks = p.chunk_blocks;
     A.n_chunks = p.n_chunks;
     A.n_qb = p.n_qb;
