@@ -26,6 +26,7 @@ PEAK = {  # MI355X published dense peaks
     "hbm_gbs": 8000.0,
     "fp32_mfma_tflops": 157.3,
     "bf16_mfma_tflops": 2500.0,
+    "fp8_mfma_tflops": 5000.0,
 }
 
 
@@ -39,7 +40,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=2)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--bf-steps", type=int, default=3)
     ap.add_argument("--no-bruteforce", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -130,10 +131,11 @@ def main():
     # the dominant kernel and its roofline (algorithmic flops of one pass)
     kernels = {k: {"avg_ms": v["ms"] / v["launches"], "launches": v["launches"],
                    "total_ms": v["ms"]} for k, v in prof.result.items()}
-    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    dom = max((k for k in kernels if k.startswith("scan_")), key=lambda k: kernels[k]["total_ms"])
     avg_s = kernels[dom]["avg_ms"] / 1e3
     flops = acc.scan_flops(Q, w.n, w.k)
-    peak = PEAK["fp32_mfma_tflops"] if dom.endswith("f32") else PEAK["bf16_mfma_tflops"]
+    peak = PEAK[{"f32": "fp32_mfma_tflops", "bf16": "bf16_mfma_tflops",
+                 "fp8": "fp8_mfma_tflops"}[dom.rsplit("_", 1)[1]]]
     achieved = flops / avg_s / 1e12
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
@@ -170,7 +172,7 @@ def main():
 
     forms = {}
     if not args.no_forms:
-        for prec in ("fp32", "bf16"):
+        for prec in ("fp32", "bf16", "fp8"):
             if prec == args.precision:
                 forms[prec] = round(qps, 1)
                 continue
@@ -190,7 +192,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "bf16",
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[args.precision],
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": 128, "k": w.k, "alpha": w.alpha,
                    "queries": Q, "query_mix": "%d perturbed + %d fresh" % (w.n_perturbed, w.n_fresh),

@@ -45,7 +45,14 @@ typedef enum {
     HN_ERR_UNSUPPORTED = -5   /* valid but not implemented (e.g. n >= 2^31) */
 } hn_status;
 
-/* Scan precision of the major-prefix pass. */
+/* Scan precision of the major-prefix pass.  FP32 scans the float32 prefix;
+ * BF16 scans round-to-nearest-even bfloat16 copies of both operands; FP8
+ * scans OCP E4M3FN copies (round to nearest even) of x[:k] / s_x and
+ * q[:k] / s_q, with power-of-two scales s_x (one per index, from max |x[:k]|)
+ * and s_q (one per query), and is available for k <= 32.  All three
+ * accumulate in float32 and keep the search exact: the bound slack covers the
+ * rounding (bf16, fp8: by the measured residual norms of the copies), and the
+ * low-precision survivors pass a float32 re-check before float64 rescoring. */
 enum { HN_PREC_FP32 = 0, HN_PREC_BF16 = 1, HN_PREC_FP8 = 2 };
 
 /* Seed that sets each query's initial lower bound. */
@@ -55,7 +62,10 @@ enum { HN_SEED_PLAIN = 0, HN_SEED_LEARNED = 1 };
 enum {
     HN_BUILD_NO_VALIDATE = 1u << 0, /* skip the block-norm check (bounds stay
                                        rigorous: they use measured norms) */
-    HN_BUILD_LOW_PRECISION = 1u << 1 /* also build the BF16 and FP8 copies */
+    HN_BUILD_LOW_PRECISION = 1u << 1 /* accepted, no effect: the BF16 copy and
+                                        (k <= 32) the FP8 copy are always
+                                        built, at 2 and 1 bytes per prefix
+                                        element */
 };
 
 typedef struct {
@@ -79,7 +89,8 @@ typedef struct {
 typedef struct {
     int64_t *seed_idx;  /* seed entry b (plain seed)                        */
     double *seed_sim;   /* L_q: the seed's canonical sim (initial bound)    */
-    float *threshold;   /* T_q: survivor test on the scan is s~ >= T_q      */
+    float *threshold;   /* T_q: survivor test on the scan is s~ >= T_q (FP8:
+                           in scan units, T_q / (s_q s_x))                 */
     int32_t *survivors; /* entries that passed the first-pass filter        */
     double *slack;      /* eps_q: rounding slack used for the bound         */
 } hn_search_aux;
@@ -151,7 +162,9 @@ int hn_filter_survivors(const hn_index *ix, const float *queries, int64_t q,
  * Phase 1 of Algorithm 1 with its score buffer: the scan scores
  * s~(q, i) = dot_K(q, x_i) (Eq. 2) as the search kernels compute them, for
  * every query and entry.
- *   precision  HN_PREC_FP32 or HN_PREC_BF16 (operands rounded to nearest).
+ *   precision  HN_PREC_FP32, HN_PREC_BF16 or HN_PREC_FP8 (k <= 32, else
+ *              HN_ERR_UNSUPPORTED); FP8 scores are returned rescaled by
+ *              s_q s_x (exact: powers of two).
  *   scores     device, float32 [q][n] row-major.
  */
 int hn_scan_scores(const hn_index *ix, const float *queries, int64_t q, int32_t precision,

@@ -75,6 +75,8 @@ namespace {
 struct BuildStats {
     unsigned long long key_major, key_minor, key_full;  // max block norms
     unsigned long long key_major16, key_res16;          // bf16 copy
+    unsigned long long key_amax;                        // max |x[:k]| (float bits)
+    unsigned long long key_major8, key_res8;            // fp8 copy
     unsigned long long bad_rows, nonfinite_rows;
     long long first_bad;
 };
@@ -83,6 +85,7 @@ __global__ void build_stats_init(BuildStats *s) {
     if (threadIdx.x == 0) {
         s->key_major = s->key_minor = s->key_full = 0;
         s->key_major16 = s->key_res16 = 0;
+        s->key_amax = s->key_major8 = s->key_res8 = 0;
         s->bad_rows = s->nonfinite_rows = 0;
         s->first_bad = 0x7fffffffffffffffll;
     }
@@ -111,7 +114,7 @@ __global__ __launch_bounds__(256) void build_norms(const float *__restrict__ db,
                                                    int k, double alpha, BuildStats *st) {
     __shared__ double sh[4];
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double nM = 0, nm = 0, nf = 0, nM16 = 0, r16 = 0;
+    double nM = 0, nm = 0, nf = 0, nM16 = 0, r16 = 0, amax = 0;
     if (i < n) {
         const float *x = db + i * kDim;
         double sM = 0, sm = 0, s16 = 0, sr = 0;
@@ -121,6 +124,7 @@ __global__ __launch_bounds__(256) void build_norms(const float *__restrict__ db,
             finite = finite && isfinite(v);
             double dv = (double)v;
             if (j < k) {
+                amax = fmax(amax, fabs(dv));
                 sM = fma(dv, dv, sM);
                 double b = (double)bf16_round(v);
                 s16 = fma(b, b, s16);
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(256) void build_norms(const float *__restrict__ db,
         }
         if (!finite) {
             atomicAdd(&st->nonfinite_rows, 1ull);
-            nM = nm = nf = nM16 = r16 = 0;
+            nM = nm = nf = nM16 = r16 = amax = 0;
         }
     }
     double a = block_max<256>(nM, sh);
@@ -152,7 +156,9 @@ __global__ __launch_bounds__(256) void build_norms(const float *__restrict__ db,
     double c = block_max<256>(nf, sh);
     double d = block_max<256>(nM16, sh);
     double e = block_max<256>(r16, sh);
+    double f = block_max<256>(amax, sh);
     if (threadIdx.x == 0) {
+        atomicMax(&st->key_amax, key_of(f));
         atomicMax(&st->key_major, key_of(a));
         atomicMax(&st->key_minor, key_of(b));
         atomicMax(&st->key_full, key_of(c));
@@ -183,6 +189,40 @@ __global__ __launch_bounds__(256) void build_major16(const float *__restrict__ d
     out[t] = (uint16_t)(__float_as_uint(bf16_round(v)) >> 16);
 }
 
+// fp8 copy: thread per row; the scale comes from the measured max |x[:k]|
+// (every thread derives the same power of two), and the row's residual
+// ||scale * fp8(x / scale) - x|| and scaled-copy norm feed the bound slack.
+__global__ __launch_bounds__(256) void build_major8(const float *__restrict__ db, int64_t n,
+                                                    int64_t n_pad, int k, int k8,
+                                                    BuildStats *st, uint8_t *__restrict__ out) {
+    __shared__ double sh[4];
+    const float scale = fp8_scale_for((float)sim_of_key(st->key_amax));
+    const float inv = 1.0f / scale;  // exact: a power of two
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double rn = 0, rr = 0;
+    if (i < n_pad) {
+        double sn = 0, sr = 0;
+        for (int c = 0; c < k8; ++c) {
+            const float v = (i < n && c < k) ? db[i * kDim + c] : 0.0f;
+            const uint8_t code = fp8_e4m3(v * inv);
+            out[i * k8 + c] = code;
+            const double back = (double)fp8_e4m3_value(code) * (double)scale;
+            sn = fma(back, back, sn);
+            sr = fma(back - (double)v, back - (double)v, sr);
+        }
+        if (i < n) {
+            rn = sqrt(sn);
+            rr = sqrt(sr);
+        }
+    }
+    const double a = block_max<256>(rn, sh);
+    const double b = block_max<256>(rr, sh);
+    if (threadIdx.x == 0) {
+        atomicMax(&st->key_major8, key_of(a));
+        atomicMax(&st->key_res8, key_of(b));
+    }
+}
+
 inline unsigned grid_for(int64_t items, int per) { return (unsigned)((items + per - 1) / per); }
 
 double key_to_double_host(unsigned long long k) {
@@ -201,6 +241,7 @@ void free_index(hn_index *ix) {
     if (ix->rows) (void)hipFree(ix->rows);
     if (ix->major32) (void)hipFree(ix->major32);
     if (ix->major16) (void)hipFree(ix->major16);
+    if (ix->major8) (void)hipFree(ix->major8);
     delete ix;
 }
 
@@ -260,6 +301,7 @@ extern "C" int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, 
     ix->alpha = alpha;
     ix->kp = f32_width(k);
     ix->kb = bf16_width(k);
+    ix->k8 = k <= 16 ? 16 : (k <= 32 ? 32 : 0);
 
     BuildStats *st = nullptr;
     auto cleanup = [&](int code) {
@@ -270,7 +312,8 @@ extern "C" int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, 
     if (hipMalloc(&st, sizeof(BuildStats)) != hipSuccess ||
         hipMalloc(&ix->rows, (size_t)n * kDim * sizeof(float)) != hipSuccess ||
         hipMalloc(&ix->major32, (size_t)ix->n_pad * ix->kp * sizeof(float)) != hipSuccess ||
-        hipMalloc(&ix->major16, (size_t)ix->n_pad * ix->kb * sizeof(uint16_t)) != hipSuccess) {
+        hipMalloc(&ix->major16, (size_t)ix->n_pad * ix->kb * sizeof(uint16_t)) != hipSuccess ||
+        (ix->k8 && hipMalloc(&ix->major8, (size_t)ix->n_pad * ix->k8) != hipSuccess)) {
         (void)hipGetLastError();
         fail(HN_ERR_OOM, "device allocation failed for n=%lld", (long long)n);
         return cleanup(HN_ERR_OOM);
@@ -281,6 +324,9 @@ extern "C" int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, 
                        db, n, ix->n_pad, k, ix->kp, ix->major32);
     hipLaunchKernelGGL(build_major16, dim3(grid_for(ix->n_pad * ix->kb, 256)), dim3(256), 0, s,
                        db, n, ix->n_pad, k, ix->kb, ix->major16);
+    if (ix->k8)
+        hipLaunchKernelGGL(build_major8, dim3(grid_for(ix->n_pad, 256)), dim3(256), 0, s, db, n,
+                           ix->n_pad, k, ix->k8, st, ix->major8);
     hipError_t e = hipMemcpyAsync(ix->rows, db, (size_t)n * kDim * sizeof(float),
                                   hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipGetLastError();
@@ -304,6 +350,15 @@ extern "C" int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, 
     ix->mu_full = round_up_norm(key_to_double_host(h.key_full));
     ix->mu_major16 = round_up_norm(key_to_double_host(h.key_major16));
     ix->res16 = round_up_norm(key_to_double_host(h.key_res16));
+    {
+        // the same power of two the device derived from the same float
+        int ex;
+        const float amax = (float)key_to_double_host(h.key_amax);
+        (void)frexpf(amax, &ex);
+        ix->scale8 = amax > 0.0f ? ldexpf(1.0f, ex - 8) : 1.0f;
+    }
+    ix->mu_major8 = round_up_norm(key_to_double_host(h.key_major8));
+    ix->res8 = round_up_norm(key_to_double_host(h.key_res8));
     (void)hipFree(st);
     *out = ix;
     return HN_OK;

@@ -94,6 +94,41 @@ __device__ __forceinline__ double sim64(const float *__restrict__ q, const float
     return acc;
 }
 
+// Round-to-nearest-even onto OCP FP8 E4M3FN (bias 7, 3 mantissa bits, no
+// infinities; magnitudes at or above 448 saturate to 448, callers scale so
+// that this never happens).  Subnormal steps are 2^-9.
+__device__ __forceinline__ uint8_t fp8_e4m3(float v) {
+    const uint32_t sign = (__float_as_uint(v) >> 31) << 7;
+    const float a = fabsf(v);
+    if (!(a > 0.0f)) return (uint8_t)sign;             // zero (and NaN, never passed)
+    if (a >= 448.0f) return (uint8_t)(sign | 0x7e);
+    if (a < 0.015625f) {                               // below 2^-6: subnormal range
+        const float m = rintf(a * 512.0f);             // multiples of 2^-9, RNE
+        return (uint8_t)(sign | (uint32_t)m);          // m == 8 is 2^-6 = code 0x08
+    }
+    int e = (int)((__float_as_uint(a) >> 23) & 0xff) - 127;  // a = 2^e * mant
+    const float mant = __uint_as_float((__float_as_uint(a) & 0x007fffffu) | 0x3f800000u);
+    int q = (int)rintf((mant - 1.0f) * 8.0f);          // 3 mantissa bits, RNE
+    if (q == 8) {
+        q = 0;
+        ++e;
+    }
+    if (e > 8 || (e == 8 && q == 7)) return (uint8_t)(sign | 0x7e);
+    return (uint8_t)(sign | (uint32_t)((e + 7) << 3) | (uint32_t)q);
+}
+__device__ __forceinline__ float fp8_e4m3_value(uint8_t c) {
+    const int e = (c >> 3) & 15, m = c & 7;
+    const float v = e == 0 ? ldexpf((float)m, -9) : ldexpf(1.0f + m * 0.125f, e - 7);
+    return (c & 0x80) ? -v : v;
+}
+// Power-of-two scale 2^(ceil(log2 amax) - 8): amax / scale <= 256 < 448.
+__host__ __device__ __forceinline__ float fp8_scale_for(float amax) {
+    if (!(amax > 0.0f)) return 1.0f;
+    int e;
+    (void)frexpf(amax, &e);  // amax = f * 2^e, 0.5 <= f < 1, so amax <= 2^e
+    return ldexpf(1.0f, e - 8);
+}
+
 // Higham's gamma_n(u).
 __host__ __device__ __forceinline__ double gamma_n(int n, double u) {
     return (double)n * u / (1.0 - (double)n * u);
@@ -115,4 +150,9 @@ struct hn_index {
     uint16_t *major16 = nullptr; // [n_pad][kb] bf16 (RNE), zero padded
     double mu_major16 = 0;       // max ||bf16(x[:k])||, rounded up
     double res16 = 0;            // max ||bf16(x[:k]) - x[:k]||, rounded up
+    int32_t k8 = 0;              // fp8 stream width (0 = not built: k > 32)
+    uint8_t *major8 = nullptr;   // [n_pad][k8] E4M3FN codes of x[:k] / scale8
+    float scale8 = 1.0f;         // power-of-two scale of the fp8 copy
+    double mu_major8 = 0;        // max ||scale8 * fp8(x[:k])||, rounded up
+    double res8 = 0;             // max ||scale8 * fp8(x[:k]) - x[:k]||, rounded up
 };

@@ -31,6 +31,7 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 
 enum ScanMode { kArgmax = 0, kFilter = 1, kWindow = 2, kStore = 3 };
 
@@ -102,6 +103,14 @@ struct Regs {  // N consecutive 32-bit values, loaded with the widest loads
     }
 };
 
+// The query operand of a tile is held as loaded (QFrag = Frag) unless the
+// tile decodes it once at load time.
+#define HN_SAME_Q_OPERAND                                                              \
+    static constexpr int kQRegs = kFragRegs;                                           \
+    typedef Frag QFrag;                                                                \
+    __device__ __forceinline__ static void load_q(QFrag &f, const Elem *p) { f.load(p); } \
+    __device__ __forceinline__ static void zero_q(QFrag &f) { f.zero(); }
+
 // float32 stream of width W on 16x16x4 MFMA (4 lane groups, W/4 each).
 template <int W>
 struct F32Tile : Shape16 {
@@ -109,6 +118,7 @@ struct F32Tile : Shape16 {
     static constexpr int kSlice = W / 4;        // elements per lane group
     static constexpr int kFragRegs = kSlice;
     typedef Regs<kFragRegs> Frag;
+    HN_SAME_Q_OPERAND
     __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
         Acc acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -126,6 +136,7 @@ struct F32Tile32 : Shape32 {
     static constexpr int kSlice = W / 2;
     static constexpr int kFragRegs = kSlice;
     typedef Regs<kFragRegs> Frag;
+    HN_SAME_Q_OPERAND
     __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
         Acc acc = {};
 #pragma unroll
@@ -144,6 +155,7 @@ struct BF16Tile : Shape16 {
     static constexpr int kSlice = W / 4;
     static constexpr int kFragRegs = kSlice / 2;
     typedef Regs<kFragRegs> Frag;
+    HN_SAME_Q_OPERAND
     __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
         Acc acc = {0.0f, 0.0f, 0.0f, 0.0f};
         if constexpr (kSlice == 4) {
@@ -172,6 +184,7 @@ struct BF16Tile32 : Shape32 {
     static constexpr int kSlice = W / 2;
     static constexpr int kFragRegs = kSlice / 2;
     typedef Regs<kFragRegs> Frag;
+    HN_SAME_Q_OPERAND
     __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
         Acc acc = {};
 #pragma unroll
@@ -185,10 +198,60 @@ struct BF16Tile32 : Shape32 {
     }
 };
 
+// FP8 (OCP E4M3FN codes) stream of width W (2 lane groups, W/2 codes each).
+// Every E4M3 value is exactly a bfloat16 value, so the codes are decoded in
+// registers (v_cvt_scalef32_pk_bf16_fp8 with scale 1, two per instruction) and
+// contracted on the 32x32x16 bf16 MFMA: the stream is half the bf16 bytes and
+// the accumulation is the bf16 matrix core's.  (The native fp8 32x32x16
+// instruction was measured to lose low-order product bits while summing, far
+// beyond float32 rounding, which no admissible slack could cover cheaply.)
+// The query operand is decoded once, at load.
+template <int W>
+struct FP8Tile32 : Shape32 {
+    typedef uint8_t Elem;
+    static constexpr int kSlice = W / 2;           // codes per lane group
+    static constexpr int kFragRegs = kSlice / 4;   // entry operand: 4 codes per register
+    static constexpr int kQRegs = kSlice / 2;      // query operand: 2 bf16 per register
+    typedef Regs<kFragRegs> Frag;
+    struct QFrag {
+        uint32_t v[kQRegs];
+    };
+    __device__ __forceinline__ static void decode(uint32_t codes, uint32_t &lo, uint32_t &hi) {
+        const v2bf a = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(codes, 1.0f, false);
+        const v2bf b = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(codes, 1.0f, true);
+        __builtin_memcpy(&lo, &a, 4);
+        __builtin_memcpy(&hi, &b, 4);
+    }
+    __device__ __forceinline__ static void load_q(QFrag &f, const Elem *p) {
+        Frag c;
+        c.load(p);
+#pragma unroll
+        for (int i = 0; i < kFragRegs; ++i) decode(c.v[i], f.v[2 * i], f.v[2 * i + 1]);
+    }
+    __device__ __forceinline__ static void zero_q(QFrag &f) {
+#pragma unroll
+        for (int i = 0; i < kQRegs; ++i) f.v[i] = 0u;
+    }
+    __device__ __forceinline__ static Acc mma(const Frag &x, const QFrag &q) {
+        Acc acc = {};
+#pragma unroll
+        for (int c = 0; c < kSlice / 8; ++c) {
+            uint32_t d[4];
+            decode(x.v[2 * c], d[0], d[1]);
+            decode(x.v[2 * c + 1], d[2], d[3]);
+            v8bf a, b;
+            __builtin_memcpy(&a, d, 16);
+            __builtin_memcpy(&b, q.v + 4 * c, 16);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        return acc;
+    }
+};
+
 // Registers one tile of a configuration holds per lane (scores + query
 // operand); a configuration is compiled when NQ times this stays within budget.
 template <class Tile>
-constexpr int tile_cost() { return Tile::kAcc + Tile::kFragRegs; }
+constexpr int tile_cost() { return Tile::kAcc + Tile::kQRegs; }
 constexpr int kTileBudget = 96;
 
 // ------------------------------------------------------------ helpers
@@ -303,6 +366,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
                                           EmitBuf &eb) {
     typedef typename Tile::Elem Elem;
     typedef typename Tile::Frag Frag;
+    typedef typename Tile::QFrag QFrag;
     typedef typename Tile::Acc Acc;
     constexpr int R = Tile::kRows, C = Tile::kCols, G = Tile::kGroups, NA = Tile::kAcc;
     constexpr int NS = kWaves / WQ;  // waves sharing one query sub-block
@@ -315,7 +379,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
 
     const Elem *xs = reinterpret_cast<const Elem *>(A.x);
     const Elem *qsrc = reinterpret_cast<const Elem *>(A.qs);
-    Frag qf[NQ];
+    QFrag qf[NQ];
     int qid[NQ];
     float thr[NQ], best[NQ];
     int bblk[NQ];
@@ -323,9 +387,9 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
     for (int t = 0; t < NQ; ++t) {
         qid[t] = (tile0 + t) * C + r;
         if (qid[t] < A.q_count)
-            qf[t].load(qsrc + (int64_t)qid[t] * A.q_stride + g * Tile::kSlice);
+            Tile::load_q(qf[t], qsrc + (int64_t)qid[t] * A.q_stride + g * Tile::kSlice);
         else
-            qf[t].zero();
+            Tile::zero_q(qf[t]);
         thr[t] = (MODE == kFilter || MODE == kWindow) ? A.thr[qid[t]] : 0.0f;
         best[t] = (MODE == kWindow && A.init_best) ? A.init_best[qid[t]] : -INFINITY;
         bblk[t] = -1;
@@ -682,11 +746,12 @@ inline int launch_tile(int mode, int cfg, const Plan &p, const ScanArgs &A, hipS
 }
 
 // Tile families: for each precision, a stream of width W up to 32 runs on the
-// 32x32 shape, wider streams on the 16x16 shape.  cost = tile_cost<Tile>().
+// 32x32 shape, wider streams on the 16x16 shape (fp8 streams are 16 or 32).  cost = tile_cost<Tile>().
 struct TileInfo {
     int rows, cols, cost, groups;
 };
 inline TileInfo tile_info(int precision, int w) {
+    if (precision == HN_PREC_FP8) return TileInfo{32, 32, 16 + w / 4, 2};
     if (precision == HN_PREC_FP32) {
         if (w <= 32) return TileInfo{32, 32, 16 + w / 2, 2};
         return TileInfo{16, 16, 4 + w / 4, 4};
@@ -702,5 +767,7 @@ int launch_scan_f32_wide(int mode, int w, int cfg, const Plan &p, const ScanArgs
                          hipStream_t s);    // widths 64, 128 (16x16 tiles)
 int launch_scan_bf16(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
                      hipStream_t s);        // widths 16, 32 (32x32), 64, 128 (16x16)
+int launch_scan_fp8(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
+                    hipStream_t s);         // widths 16, 32 (32x32)
 
 }  // namespace hn

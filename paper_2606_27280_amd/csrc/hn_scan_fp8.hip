@@ -1,0 +1,13 @@
+// FP8 (E4M3FN) scan kernels: widths 16 and 32, decoded to bf16 in registers
+// for the 32x32x16 MFMA shape.
+#include "hn_scan.h"
+
+namespace hn {
+int launch_scan_fp8(int mode, int w, int cfg, const Plan &p, const ScanArgs &A, hipStream_t s) {
+    switch (w) {
+        case 16: return launch_tile<FP8Tile32<16>, false>(mode, cfg, p, A, s);
+        case 32: return launch_tile<FP8Tile32<32>, false>(mode, cfg, p, A, s);
+    }
+    return 1;
+}
+}  // namespace hn

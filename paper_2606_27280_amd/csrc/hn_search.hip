@@ -25,8 +25,9 @@ constexpr int kWorkWords = 32;
 struct QNorm {
     double major, minor, full;  // rounded-up float64 block norms
     double res16;               // ||bf16(q[:k]) - q[:k]||, rounded up
+    double res8;                // ||s8 fp8(q[:k] / s8) - q[:k]||, rounded up
+    float sc8;                  // s8: power-of-two scale of the fp8 operand
     int bad;                    // non-finite component
-    int pad_;
 };
 
 __device__ __forceinline__ float bf16_rne(float f) {
@@ -35,25 +36,37 @@ __device__ __forceinline__ float bf16_rne(float f) {
     return __uint_as_float(u & 0xffff0000u);
 }
 
-// One thread per (padded) query: norms and the float32 / bf16 operands.
-__global__ __launch_bounds__(256) void prep_queries(const float *__restrict__ q, int64_t nq,
-                                                    int64_t q_pad, int k, int w32, int w16,
-                                                    float *__restrict__ op32,
-                                                    uint16_t *__restrict__ op16,
-                                                    QNorm *__restrict__ qn,
-                                                    unsigned *__restrict__ work) {
+// Query operands for the scans (any pointer may be NULL), widths per stream.
+struct PrepArgs {
+    const float *q;
+    int64_t nq, q_pad;
+    int k;
+    int w32, w16, w8;
+    float *op32;
+    uint16_t *op16;
+    uint8_t *op8;
+    QNorm *qn;
+    unsigned *work;
+};
+
+// One thread per (padded) query: norms and the float32 / bf16 / fp8 operands.
+__global__ __launch_bounds__(256) void prep_queries(PrepArgs P) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (work && i < kWorkWords) work[i] = 0u;
-    if (i >= q_pad) return;
-    if (i >= nq) {
-        if (op32)
-            for (int c = 0; c < w32; ++c) op32[i * w32 + c] = 0.0f;
-        if (op16)
-            for (int c = 0; c < w16; ++c) op16[i * w16 + c] = 0;
+    if (P.work && i < kWorkWords) P.work[i] = 0u;
+    if (i >= P.q_pad) return;
+    if (i >= P.nq) {
+        if (P.op32)
+            for (int c = 0; c < P.w32; ++c) P.op32[i * P.w32 + c] = 0.0f;
+        if (P.op16)
+            for (int c = 0; c < P.w16; ++c) P.op16[i * P.w16 + c] = 0;
+        if (P.op8)
+            for (int c = 0; c < P.w8; ++c) P.op8[i * P.w8 + c] = 0;
         return;
     }
-    const float *v = q + i * kDim;
+    const int k = P.k;
+    const float *v = P.q + i * kDim;
     double sM = 0, sm = 0, sr = 0;
+    float amax = 0.0f;
     bool finite = true;
     for (int j = 0; j < kDim; ++j) {
         float f = v[j];
@@ -63,6 +76,7 @@ __global__ __launch_bounds__(256) void prep_queries(const float *__restrict__ q,
             sM = fma(d, d, sM);
             double b = (double)bf16_rne(f);
             sr = fma(b - d, b - d, sr);
+            amax = fmaxf(amax, fabsf(f));
         } else {
             sm = fma(d, d, sm);
         }
@@ -73,15 +87,30 @@ __global__ __launch_bounds__(256) void prep_queries(const float *__restrict__ q,
     r.minor = sqrt(sm) * up;
     r.full = sqrt(sM + sm) * up;
     r.res16 = sqrt(sr) * up;
+    r.res8 = 0.0;
+    r.sc8 = 1.0f;
     r.bad = finite ? 0 : 1;
-    r.pad_ = 0;
-    qn[i] = r;
-    if (op32)
-        for (int c = 0; c < w32; ++c) op32[i * w32 + c] = (c < k && finite) ? v[c] : 0.0f;
-    if (op16)
-        for (int c = 0; c < w16; ++c)
-            op16[i * w16 + c] =
+    if (P.op32)
+        for (int c = 0; c < P.w32; ++c) P.op32[i * P.w32 + c] = (c < k && finite) ? v[c] : 0.0f;
+    if (P.op16)
+        for (int c = 0; c < P.w16; ++c)
+            P.op16[i * P.w16 + c] =
                 (c < k && finite) ? (uint16_t)(__float_as_uint(bf16_rne(v[c])) >> 16) : 0;
+    if (P.op8) {
+        const float sc = finite ? fp8_scale_for(amax) : 1.0f;
+        const float inv = 1.0f / sc;  // exact: a power of two
+        double s8 = 0;
+        for (int c = 0; c < P.w8; ++c) {
+            const float f = (c < k && finite) ? v[c] : 0.0f;
+            const uint8_t code = fp8_e4m3(f * inv);
+            P.op8[i * P.w8 + c] = code;
+            const double e = (double)fp8_e4m3_value(code) * (double)sc - (double)f;
+            s8 = fma(e, e, s8);
+        }
+        r.res8 = sqrt(s8) * up;
+        r.sc8 = sc;
+    }
+    P.qn[i] = r;
 }
 
 // ---------------------------------------------------------------- seed
@@ -98,11 +127,14 @@ struct SeedArgs {
     int32_t k;
     double alpha, beta;  // beta = alpha for exact search
     double mu_major, mu_minor, mu_full;
-    // scan slack: eps_scan = min(rel_a * major * mu_a, rel_b * major * mu_b +
-    //                            res_q_coef * res16 + res_x * major) + abs
+    // scan slack: worst case rel * major * mu, or the residual-norm form
+    // res_q * res_mu + major * res_x + acc_rel * (major + res_q) * res_mu,
+    // or the smaller of the two; plus abs
     double scan_rel, scan_mu, scan_abs;
-    int scan_res;  // use the residual-norm form as a second rigorous bound
-    double res_mu, res_x, res_acc_rel, res_acc_mu;
+    int scan_res;  // 0: worst case; 1: min(worst case, residual); 2: residual
+    int fp8;       // residuals of the fp8 operands; thresholds in scan units
+    double res_mu, res_x, res_acc_rel;
+    double scale_x;  // fp8: power-of-two scale of the entry copy
     const double *lower;  // given L (filter-only); NULL: plain seed
     const QNorm *qn;
     float *thr;           // [q_pad]: scan threshold T_q (+inf for padding)
@@ -197,15 +229,19 @@ __global__ __launch_bounds__(256) void seed_kernel(SeedArgs S) {
     // slack: scan rounding + stored-norm excess (Eq. 3) + float64 evaluation
     double es = S.scan_rel * qn.major * S.scan_mu;
     if (S.scan_res) {
-        double er = qn.res16 * S.res_mu + qn.major * S.res_x +
-                    S.res_acc_rel * (qn.major + qn.res16) * S.res_acc_mu;
-        es = fmin(es, er);
+        const double rq = S.fp8 ? qn.res8 : qn.res16;
+        const double er =
+            rq * S.res_mu + qn.major * S.res_x + S.res_acc_rel * (qn.major + rq) * S.res_mu;
+        es = S.scan_res == 2 ? er : fmin(es, er);
     }
     es += S.scan_abs;
     double en = fmax(0.0, qn.minor * S.mu_minor - S.alpha);
     double e64 = gamma_n(kDim, kU64) * qn.full * S.mu_full;
     double eps = (es + en + e64) * (1.0 + ldexp(1.0, -30)) + ldexp(1.0, -40);
-    S.thr[i] = round_down_f32(L - S.beta - eps);
+    // fp8 scans score q~ . x~ with q = s_q q~ and x = s_x x~ (powers of two):
+    // the threshold in scan units is the same bound divided by s_q s_x, exact
+    const double unit = S.fp8 ? 1.0 / ((double)qn.sc8 * S.scale_x) : 1.0;
+    S.thr[i] = round_down_f32((L - S.beta - eps) * unit);
     if (S.thr32) {
         double e32 = gamma_n(S.k, kU32) * qn.major * S.mu_major + S.k * ldexp(1.0, -125);
         double eps32 = (e32 + en + e64) * (1.0 + ldexp(1.0, -30)) + ldexp(1.0, -40);
@@ -470,12 +506,12 @@ unsigned blocks_for(int64_t items, int per = 256) {
 
 // precision 0: float32 stream of width w; 1: bf16 stream of width w.
 const char *scan_tag(int mode, int precision) {
-    static const char *const tags[4][2] = {
-        {"scan_argmax_f32", "scan_argmax_bf16"},
-        {"scan_filter_f32", "scan_filter_bf16"},
-        {"scan_window_f32", "scan_window_bf16"},
-        {"scan_store_f32", "scan_store_bf16"}};
-    return tags[mode][precision == HN_PREC_FP32 ? 0 : 1];
+    static const char *const tags[4][3] = {
+        {"scan_argmax_f32", "scan_argmax_bf16", "scan_argmax_fp8"},
+        {"scan_filter_f32", "scan_filter_bf16", "scan_filter_fp8"},
+        {"scan_window_f32", "scan_window_bf16", "scan_window_fp8"},
+        {"scan_store_f32", "scan_store_bf16", "scan_store_fp8"}};
+    return tags[mode][precision == HN_PREC_FP32 ? 0 : (precision == HN_PREC_BF16 ? 1 : 2)];
 }
 
 template <int MODE>
@@ -488,6 +524,8 @@ int launch_scan(int precision, int w, int cfg, const Plan &p, const ScanArgs &A,
                      : launch_scan_f32_wide(MODE, w, cfg, p, A, s);
     else if (precision == HN_PREC_BF16)
         rc = launch_scan_bf16(MODE, w, cfg, p, A, s);
+    else if (precision == HN_PREC_FP8)
+        rc = launch_scan_fp8(MODE, w, cfg, p, A, s);
     else
         return fail(HN_ERR_UNSUPPORTED, "precision %d is not available", precision);
     if (rc) return fail(HN_ERR_INVALID_ARG, "no scan kernel for mode %d width %d config %d", MODE, w, cfg);
@@ -506,6 +544,7 @@ struct Work {
     const void *stream_x = nullptr;
     float *op32 = nullptr;
     uint16_t *op16 = nullptr;
+    uint8_t *op8 = nullptr;
     QNorm *qn = nullptr;
     float *part_val = nullptr;
     int32_t *part_idx = nullptr;
@@ -521,10 +560,52 @@ struct Work {
     int64_t cap = 0;
 };
 
+// The scan stream and query operands of a precision.
+int stream_width(const hn_index *ix, int precision) {
+    return precision == HN_PREC_FP32 ? ix->kp : (precision == HN_PREC_BF16 ? ix->kb : ix->k8);
+}
+const void *stream_of(const hn_index *ix, int precision) {
+    return precision == HN_PREC_FP32   ? (const void *)ix->major32
+           : precision == HN_PREC_BF16 ? (const void *)ix->major16
+                                       : (const void *)ix->major8;
+}
+const void *operands_of(const Work &W) {
+    return W.precision == HN_PREC_FP32   ? (const void *)W.op32
+           : W.precision == HN_PREC_BF16 ? (const void *)W.op16
+                                         : (const void *)W.op8;
+}
+
+int check_precision(const hn_index *ix, int precision) {
+    if (precision != HN_PREC_FP32 && precision != HN_PREC_BF16 && precision != HN_PREC_FP8)
+        return fail(HN_ERR_UNSUPPORTED, "precision %d is not available", precision);
+    if (precision == HN_PREC_FP8 && ix->k8 == 0)
+        return fail(HN_ERR_UNSUPPORTED, "the fp8 scan needs k <= 32 (k = %d)", ix->k);
+    return HN_OK;
+}
+
+void launch_prep(const hn_index *ix, const float *queries, int64_t q, const Plan &p, Work &W,
+                 hipStream_t s) {
+    PrepArgs P;
+    P.q = queries;
+    P.nq = q;
+    P.q_pad = p.q_pad;
+    P.k = ix->k;
+    P.w32 = ix->kp;
+    P.w16 = ix->kb;
+    P.w8 = ix->k8;
+    P.op32 = W.op32;
+    P.op16 = W.op16;
+    P.op8 = W.op8;
+    P.qn = W.qn;
+    P.work = W.work;
+    ProfScope prof_(s, "prep_queries");
+    hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, P);
+}
+
 int validate_opts(const hn_index *ix, const hn_search_opts *o) {
     if (!o) return HN_OK;
-    if (o->precision != HN_PREC_FP32 && o->precision != HN_PREC_BF16)
-        return fail(HN_ERR_UNSUPPORTED, "precision %d is not available", o->precision);
+    int rc = check_precision(ix, o->precision);
+    if (rc) return rc;
     if (o->seed != HN_SEED_PLAIN) return fail(HN_ERR_UNSUPPORTED, "seed %d is not available", o->seed);
     if (o->query_tiles != 0 && o->query_tiles != 1 && o->query_tiles != 2 && o->query_tiles != 4 &&
         o->query_tiles != 8)
@@ -541,8 +622,8 @@ int validate_opts(const hn_index *ix, const hn_search_opts *o) {
 int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_search_opts &o,
                const double *lower, int64_t cap, Work &W, hipStream_t s) {
     W.precision = o.precision;
-    W.width = W.precision == HN_PREC_FP32 ? ix->kp : ix->kb;
-    W.stream_x = W.precision == HN_PREC_FP32 ? (const void *)ix->major32 : (const void *)ix->major16;
+    W.width = stream_width(ix, W.precision);
+    W.stream_x = stream_of(ix, W.precision);
     const TileInfo ti = tile_info(W.precision, W.width);
     W.cfg = pick_cfg(q, ti.cols, ti.cost, o.query_tiles);
     if (W.cfg < 0)
@@ -557,6 +638,7 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     auto add = [&](size_t count, size_t sz) { bytes += (count * sz + 255) & ~size_t(255); };
     add(p.q_pad * ix->kp, 4);
     add(p.q_pad * ix->kb, 2);
+    add(p.q_pad * ix->k8, 1);
     add(p.q_pad, sizeof(QNorm));
     add((size_t)p.n_chunks * p.q_pad, 4);
     add((size_t)p.n_chunks * p.q_pad, 4);
@@ -579,6 +661,7 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     if (rc) return rc;
     W.op32 = ar->take<float>(p.q_pad * ix->kp);
     W.op16 = ar->take<uint16_t>(p.q_pad * ix->kb);
+    W.op8 = ix->k8 ? ar->take<uint8_t>(p.q_pad * ix->k8) : nullptr;
     W.qn = ar->take<QNorm>(p.q_pad);
     W.part_val = ar->take<float>((size_t)p.n_chunks * p.q_pad);
     W.part_idx = ar->take<int32_t>((size_t)p.n_chunks * p.q_pad);
@@ -598,18 +681,14 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     W.pairs = ar->take<int2>(cap);
     W.psim = ar->take<double>(cap);
 
-    {
-        ProfScope prof_(s, "prep_queries");
-        hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, queries, q,
-                           p.q_pad, ix->k, ix->kp, ix->kb, W.op32, W.op16, W.qn, W.work);
-    }
+    launch_prep(ix, queries, q, p, W, s);
     HN_HIP(hipGetLastError());
 
     ScanArgs A;
     memset(&A, 0, sizeof A);
     A.x = W.stream_x;
     A.x_stride = W.width;
-    A.qs = W.precision == HN_PREC_FP32 ? (const void *)W.op32 : (const void *)W.op16;
+    A.qs = operands_of(W);
     A.q_stride = W.width;
     A.n = ix->n;
     A.n_blocks = p.n_blocks;
@@ -651,7 +730,7 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
         S.scan_mu = ix->mu_major;
         S.scan_abs = ix->k * ldexp(1.0, -125);
         S.scan_res = 0;
-    } else {
+    } else if (W.precision == HN_PREC_BF16) {
         // worst case: both roundings relative 2^-8, then float32 accumulation
         const double ub = kUbf16;
         S.scan_rel = (2 * ub + ub * ub) + gamma_n(ix->k, kU32) * (1 + ub) * (1 + ub);
@@ -663,7 +742,19 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
         S.res_mu = ix->mu_major16;
         S.res_x = ix->res16;
         S.res_acc_rel = gamma_n(ix->k, kU32);
-        S.res_acc_mu = ix->mu_major16;
+    } else {
+        // fp8: the residual form only (subnormal codes have no relative
+        // bound); the products are summed by the bf16 matrix core (the codes
+        // are decoded exactly to bf16), float32 accumulation.
+        S.scan_rel = 0.0;
+        S.scan_mu = 0.0;
+        S.scan_abs = ix->k * ldexp(1.0, -125);
+        S.scan_res = 2;
+        S.fp8 = 1;
+        S.scale_x = ix->scale8;
+        S.res_mu = ix->mu_major8;
+        S.res_x = ix->res8;
+        S.res_acc_rel = gamma_n(ix->k, kU32);
     }
     S.lower = lower;
     S.qn = W.qn;
@@ -691,7 +782,7 @@ ScanArgs filter_args(const hn_index *ix, const Work &W, int64_t q, int2 *pairs, 
     memset(&A, 0, sizeof A);
     A.x = W.stream_x;
     A.x_stride = W.width;
-    A.qs = W.precision == HN_PREC_FP32 ? (const void *)W.op32 : (const void *)W.op16;
+    A.qs = operands_of(W);
     A.q_stride = W.width;
     A.n = ix->n;
     A.n_blocks = p.n_blocks;
@@ -709,6 +800,14 @@ ScanArgs filter_args(const hn_index *ix, const Work &W, int64_t q, int2 *pairs, 
     A.redo = W.redo;
     A.redo_count = W.work + 2 * kXcds + 1;
     return A;
+}
+
+__global__ __launch_bounds__(256) void scale_scores(float *scores, int64_t q, int64_t n,
+                                                   const QNorm *qn, float scale_x) {
+    const int64_t total = q * n;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * 256)
+        scores[t] *= qn[t / n].sc8 * scale_x;
 }
 
 int64_t default_cap(int64_t n, int64_t q) {
@@ -871,38 +970,40 @@ extern "C" int hn_scan_scores(const hn_index *ix, const float *queries, int64_t 
     if (!ix) return fail(HN_ERR_INVALID_ARG, "null index");
     if (q < 0) return fail(HN_ERR_INVALID_ARG, "q must be >= 0");
     if (q > 0 && (!queries || !scores)) return fail(HN_ERR_INVALID_ARG, "null queries or scores");
-    if (precision != HN_PREC_FP32 && precision != HN_PREC_BF16)
-        return fail(HN_ERR_UNSUPPORTED, "precision %d is not available", precision);
+    int rc = check_precision(ix, precision);
+    if (rc) return rc;
     if (q == 0) return HN_OK;
     hipStream_t s = (hipStream_t)stream;
-    hn_search_opts o{precision, HN_SEED_PLAIN, 0, 0, 0, -1.0};
     Work W;
     W.precision = precision;
-    W.width = precision == HN_PREC_FP32 ? ix->kp : ix->kb;
+    W.width = stream_width(ix, precision);
     W.cfg = 0;
     const TileInfo ti = tile_info(precision, W.width);
     W.plan = make_plan(ix->n, q, W.cfg, 0, ti.rows, ti.cols);
-    (void)o;
     const Plan &p = W.plan;
-    size_t bytes = ((p.q_pad * ix->kp * 4 + 255) & ~size_t(255)) +
-                   ((p.q_pad * ix->kb * 2 + 255) & ~size_t(255)) +
-                   ((p.q_pad * sizeof(QNorm) + 255) & ~size_t(255)) + 256 +
-                   ((p.n_items * 4 + 255) & ~size_t(255));
+    size_t bytes = 0;
+    auto add = [&](size_t count, size_t sz) { bytes += (count * sz + 255) & ~size_t(255); };
+    add(p.q_pad * ix->kp, 4);
+    add(p.q_pad * ix->kb, 2);
+    add(p.q_pad * ix->k8, 1);
+    add(p.q_pad, sizeof(QNorm));
+    add(kWorkWords, 4);
+    add(p.n_items, 4);
     Arena *ar = nullptr;
-    int rc = arena_for(stream, bytes, &ar);
+    rc = arena_for(stream, bytes, &ar);
     if (rc) return rc;
     W.op32 = ar->take<float>(p.q_pad * ix->kp);
     W.op16 = ar->take<uint16_t>(p.q_pad * ix->kb);
+    W.op8 = ix->k8 ? ar->take<uint8_t>(p.q_pad * ix->k8) : nullptr;
     W.qn = ar->take<QNorm>(p.q_pad);
     W.work = ar->take<unsigned>(kWorkWords);
     W.redo = ar->take<int>(p.n_items);
-    hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, queries, q,
-                       p.q_pad, ix->k, ix->kp, ix->kb, W.op32, W.op16, W.qn, W.work);
+    launch_prep(ix, queries, q, p, W, s);
     ScanArgs A;
     memset(&A, 0, sizeof A);
-    A.x = precision == HN_PREC_FP32 ? (const void *)ix->major32 : (const void *)ix->major16;
+    A.x = stream_of(ix, precision);
     A.x_stride = W.width;
-    A.qs = precision == HN_PREC_FP32 ? (const void *)W.op32 : (const void *)W.op16;
+    A.qs = operands_of(W);
     A.q_stride = W.width;
     A.n = ix->n;
     A.n_blocks = p.n_blocks;
@@ -915,7 +1016,13 @@ extern "C" int hn_scan_scores(const hn_index *ix, const float *queries, int64_t 
     A.scores = scores;
     A.redo = W.redo;
     A.redo_count = W.work + 2 * kXcds;
-    return launch_scan<kStore>(precision, W.width, W.cfg, p, A, s);
+    rc = launch_scan<kStore>(precision, W.width, W.cfg, p, A, s);
+    if (rc || precision != HN_PREC_FP8) return rc;
+    // fp8 scores come out in units of s_q s_x: rescale (exact, powers of two)
+    hipLaunchKernelGGL(scale_scores, dim3(2048), dim3(256), 0, s, scores, q, ix->n, W.qn,
+                       ix->scale8);
+    HN_HIP(hipGetLastError());
+    return HN_OK;
 }
 
 extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const float *queries,
@@ -988,8 +1095,17 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
         ProfScope prof_(s, "bf_db_norm");
         hipLaunchKernelGGL(bf_db_norm, dim3(blocks_for(n)), dim3(256), 0, s, db, n, mu_key);
     }
-    hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, queries, q,
-                       p.q_pad, kDim - 1, 0, 0, (float *)nullptr, (uint16_t *)nullptr, qn, work);
+    {
+        PrepArgs P;
+        memset(&P, 0, sizeof P);
+        P.q = queries;
+        P.nq = q;
+        P.q_pad = p.q_pad;
+        P.k = kDim - 1;
+        P.qn = qn;
+        P.work = work;
+        hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, P);
+    }
     BfPrepArgs P{qn, mu_key, q, p.q_pad, win_scan, win, best_key, best_idx, cnt, qflag, counter};
     {
         ProfScope prof_(s, "bf_prep");

@@ -80,6 +80,60 @@ def test_scan_scores_bf16_within_rounding_bound(hn, k):
     assert (err <= bound + k * 2.0 ** -125 + 1e-15).all(), (err - bound).max()
     # and the rounding really happened (this is not the float32 path)
     assert err.max() > 1e-5
+    # the matrix core sums the exact products of the rounded operands with
+    # float32-sized error (torch's round-to-nearest-even bf16 cast)
+    import torch
+    q16 = torch.from_numpy(qs[:, :k]).to(torch.bfloat16).double().numpy()
+    x16 = torch.from_numpy(db[:, :k]).to(torch.bfloat16).double().numpy()
+    gam = k * 2.0 ** -23 / (1 - k * 2.0 ** -23)
+    d = np.abs(got - q16 @ x16.T)
+    assert (d <= gam * (np.abs(q16) @ np.abs(x16).T) + 1e-30).all(), d.max()
+    ix.close()
+
+
+def _fp8_copy(a):
+    """OCP E4M3FN copy (round to nearest even, torch's CPU cast) of a float32
+    matrix with the power-of-two scale 2^(e - 8), amax = f 2^e, 0.5 <= f < 1:
+    returns (scale, float64 values of the scaled codes times the scale)."""
+    import torch
+    amax = float(np.abs(a).max())
+    scale = 1.0 if amax == 0 else math.ldexp(1.0, math.frexp(amax)[1] - 8)
+    codes = torch.from_numpy(np.ascontiguousarray(a / np.float32(scale), dtype=np.float32))
+    back = codes.to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    assert np.isfinite(back).all()
+    return scale, back * scale
+
+
+@pytest.mark.parametrize("k", [1, 8, 16, 30, 32])
+def test_scan_scores_fp8_exact_products_and_bound(hn, k):
+    """The fp8 scan score is the float32 sum of exact E4M3 products, rescaled
+    (the codes are contracted on the bf16 matrix core):
+    it matches the float64 dot of the quantised operands up to float32
+    accumulation, and the true prefix dot within the residual-norm bound the
+    search's slack uses."""
+    alpha = 1 / 8
+    db = hn_inputs.make_db(1003, k, alpha, 9, 500 + k)
+    qs = hn_inputs.make_queries(db, k, alpha, 28, 9, 600 + k)
+    qs[0, :k] *= 1e-4  # a query with tiny components: subnormal fp8 codes
+    say("scan_scores fp8 k=%d n=1003 q=37" % k)
+    ix = hn.Index(dev(db), k, alpha, flags=hn.HN_BUILD_NO_VALIDATE)
+    got = ix.scan_scores(dev(qs), "fp8").cpu().numpy().astype(np.float64)
+    _, x8 = _fp8_copy(db[:, :k])
+    q8 = np.stack([_fp8_copy(q[None, :k])[1][0] for q in qs])
+    quant = q8 @ x8.T  # exact: products of E4M3 values, few terms
+    acc = np.abs(q8) @ np.abs(x8).T
+    gam = k * 2.0 ** -23 / (1 - k * 2.0 ** -23)
+    d = np.abs(got - quant)
+    assert (d <= gam * acc + 1e-30).all(), d.max()
+    ref = qs[:, :k].astype(np.float64) @ db[:, :k].astype(np.float64).T
+    rx = np.sqrt(((x8 - db[:, :k]) ** 2).sum(1)).max()
+    mu8 = np.sqrt((x8 ** 2).sum(1)).max()
+    rq = np.sqrt(((q8 - qs[:, :k]) ** 2).sum(1))
+    nq = np.sqrt((qs[:, :k].astype(np.float64) ** 2).sum(1))
+    bound = rq[:, None] * mu8 + nq[:, None] * rx + gam * (nq + rq)[:, None] * mu8
+    assert (np.abs(got - ref) <= bound + 1e-15).all()
+    if k > 1:
+        assert np.abs(got - ref).max() > 1e-4  # the quantisation really happened
     ix.close()
 
 
@@ -97,12 +151,12 @@ def _check_search(hn, db, qs, k, alpha, precision="fp32", what="", **kw):
     return ref, out, st
 
 
-def test_workload1_fp32_and_bf16_exact(hn):
+def test_workload1_all_precisions_exact(hn):
     w = hn_inputs.workload(1)
     db = w.db()
     qs = w.queries(db)
     bi, bs = oracle.bruteforce_top1(db, qs)
-    for prec in ("fp32", "bf16"):
+    for prec in ("fp32", "bf16", "fp8"):
         ref, aux, st = _check_search(hn, db, qs, w.k, w.alpha, prec, "workload1")
         assert (ref["idx"] == bi).all()
         assert st["overflow_queries"] == 0
@@ -127,7 +181,9 @@ def test_edge_shapes_exact(hn, n, k, alpha, nq):
     if n >= 8:  # exact ties: duplicated rows
         db[n - 1] = db[0]
         db[n // 2] = db[3]
-    for prec in ("fp32", "bf16"):
+    for prec in ("fp32", "bf16", "fp8"):
+        if prec == "fp8" and k > 32:
+            continue  # no fp8 copy above k = 32 (checked in test_invalid_inputs)
         _check_search(hn, db, qs, k, alpha, prec, "edge")
 
 
@@ -139,7 +195,7 @@ def test_tie_rule_golden_on_gpu(hn):
     db[:, :4] = np.array(g["db"], dtype=np.float32)
     q = np.zeros((1, 128), dtype=np.float32)
     q[0, :4] = g["query"]
-    for prec in ("fp32", "bf16"):
+    for prec in ("fp32", "bf16", "fp8"):
         ref, aux, _ = _check_search(hn, db, q, g["k"], g["alpha"], prec, "tie-golden",
                                     flags=hn.HN_BUILD_NO_VALIDATE)
         assert ref["idx"][0] == g["expected_idx"]
@@ -201,9 +257,16 @@ def test_invalid_inputs(hn):
     with pytest.raises(ValueError):
         ix.search(dev(qs).double())
     with pytest.raises(hn.HNError):
-        ix.search(dev(qs), precision="fp8")
+        ix.search(dev(qs), precision=7)
     with pytest.raises(hn.HNError):
         ix.search(dev(qs), beta=0.5)
+    ix.close()
+    say("fp8 on k = 40 (no fp8 copy)")
+    db40 = hn_inputs.make_db(300, 40, alpha, 3, 8)
+    ix = hn.Index(dev(db40), 40, alpha)
+    with pytest.raises(hn.HNError) as e:
+        ix.search(dev(hn_inputs.make_queries(db40, 40, alpha, 4, 1, 9)), precision="fp8")
+    assert e.value.code == -5
     ix.close()
     with pytest.raises(hn.HNError):
         hn.Index(dev(db[:, :64]), k, alpha)
@@ -303,16 +366,18 @@ def test_workload2_full_size_sampled(hn):
     w = hn_inputs.workload(2)
     db = w.db()
     qs = w.queries(db)
-    say("workload2 full: build + search fp32/bf16 + bruteforce")
+    say("workload2 full: build + search fp32/bf16/fp8 + bruteforce")
     ix = hn.Index(dev(db), w.k, w.alpha)
     dq = dev(qs)
     i32, s32, aux, st = ix.search(dq, aux=True, stats=True)
     i16, s16 = ix.search(dq, precision="bf16")
+    i8, s8 = ix.search(dq, precision="fp8")
     bi, bs = hn.bruteforce_top1(dev(db), dq)
-    i32, s32, i16, s16 = (t.cpu().numpy() for t in (i32, s32, i16, s16))
+    i32, s32, i16, s16, i8, s8 = (t.cpu().numpy() for t in (i32, s32, i16, s16, i8, s8))
     bi, bs = bi.cpu().numpy(), bs.cpu().numpy()
     assert (i32 == bi).all() and np.array_equal(s32, bs)
     assert (i16 == bi).all() and np.array_equal(s16, bs)
+    assert (i8 == bi).all() and np.array_equal(s8, bs)
     assert st["overflow_queries"] == 0
     sample = np.arange(0, len(qs), 20)
     ref = oracle.bnb_top1(db, qs[sample], w.k, w.alpha)
