@@ -87,6 +87,19 @@ def uniform_draws(n: int, seed: int) -> np.ndarray:
     return np.random.Generator(np.random.PCG64(seed)).random(n)
 
 
+def mlp_init(seed: int, sizes=(128, 256, 256, 512)) -> np.ndarray:
+    """Initial seed-model parameters, float32, in the flat layout W1, b1, W2,
+    b2, W3, b3 (weights [out][in]): every value uniform in
+    [-1/sqrt(in), 1/sqrt(in)] of its layer."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for fan_in, fan_out in zip(sizes[:-1], sizes[1:]):
+        lim = 1.0 / math.sqrt(fan_in)
+        parts.append(rng.uniform(-lim, lim, size=fan_out * fan_in))
+        parts.append(rng.uniform(-lim, lim, size=fan_out))
+    return np.concatenate(parts).astype(np.float32)
+
+
 @dataclass
 class Workload:
     name: str
@@ -108,6 +121,12 @@ class Workload:
             db = self.db()
         return make_queries(db, self.k, self.alpha, self.n_perturbed,
                             self.n_fresh, self.q_seed)
+
+    def train_queries(self, db: np.ndarray) -> np.ndarray:
+        """The learned seed's training queries (perturbed entries, a stream of
+        their own, disjoint from the held-out queries' seed)."""
+        return make_queries(db, self.k, self.alpha, self.extra["n_train"], 0,
+                            self.extra["train_seed"])
 
 
 def workload(idx: int, scale: float = 1.0) -> Workload:

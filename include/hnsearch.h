@@ -55,8 +55,27 @@ typedef enum {
  * low-precision survivors pass a float32 re-check before float64 rescoring. */
 enum { HN_PREC_FP32 = 0, HN_PREC_BF16 = 1, HN_PREC_FP8 = 2 };
 
-/* Seed that sets each query's initial lower bound. */
-enum { HN_SEED_PLAIN = 0, HN_SEED_LEARNED = 1 };
+/* How each query's initial lower bound L_q is found (Algorithm 1 step 2).
+ *   PLAIN    two scans: the argmax scan gives the seed b (largest scan score),
+ *            L_q = sim(q, x_b); the filter scan keeps s~ >= T_q.
+ *   LEARNED  one scan: L_q from the index's seed model (hn_set_seed_model), the
+ *            best canonical sim among the anchors of the model's 4 largest
+ *            outputs; the scan keeps s~ >= max(T_q, m - w_q), m the running
+ *            scan maximum of its work item and w_q = 2 (alpha + eps_q): the
+ *            entry scoring m has sim >= m - alpha - eps_q, so anything below
+ *            the window cannot beat it.  Survivors are re-filtered against the
+ *            final maximum, then rescored.
+ *   WINDOW   one scan with the window only (L_q = -inf): the comparison form
+ *            without a seed. */
+enum { HN_SEED_PLAIN = 0, HN_SEED_LEARNED = 1, HN_SEED_WINDOW = 2 };
+
+/* The seed model: an MLP 128 -> 256 -> 256 -> 512 with exact GELU
+ * (x Phi(x)) after the two hidden layers, bf16 weights, float32 biases,
+ * float32 accumulation, one output per anchor entry.  Its parameters are one
+ * float32 vector of HN_MLP_PARAMS values: W1 [256][128], b1 [256],
+ * W2 [256][256], b2 [256], W3 [512][256], b3 [512], weights row-major
+ * (output-major).  Forward passes round the weights to bf16 (nearest even). */
+enum { HN_MLP_IN = 128, HN_MLP_H = 256, HN_MLP_OUT = 512, HN_MLP_PARAMS = 230400 };
 
 /* Build flags. */
 enum {
@@ -196,6 +215,68 @@ int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const float *queri
 int hn_profile_begin(void *stream);
 int hn_profile_end(void *stream, const char **names, double *ms, int64_t *counts, int32_t max,
                    int32_t *n_out);
+
+/* ---------------------------------------------------------------- seed model
+ * Not part of the paper: the learned seed of the spec form.  Anchors are
+ * chosen by k-means++ D^2 seeding, a query's label is the anchor closest to
+ * its exact nearest neighbour, and the MLP is trained with softmax
+ * cross-entropy and AdamW.  All pointers are device memory. */
+
+typedef struct {
+    double lr, beta1, beta2, eps, weight_decay; /* AdamW, decoupled decay:
+        w -= lr (m^ / (sqrt(v^) + eps) + weight_decay w) */
+} hn_adamw_opts;
+
+/* logits [b][512] = MLP(x [b][128]) for the float32 parameter vector
+ * `params` (weights rounded to bf16).  0 <= b <= 2^24. */
+int hn_mlp_forward(const float *params, const float *x, int64_t b, float *logits, void *stream);
+
+/* Gradient of the mean softmax cross-entropy of MLP(x) against labels
+ * (int32 [b], each in [0, 512); another value makes the loss NaN) with
+ * respect to the parameters: grads [HN_MLP_PARAMS] in the parameter layout,
+ * loss: one float.  The forward rounds the weights to bf16; the gradient is
+ * taken through that forward (straight through to the float32 weights).
+ * 1 <= b <= 2^20. */
+int hn_mlp_grad(const float *params, const float *x, const int32_t *labels, int64_t b,
+                float *grads, float *loss, void *stream);
+
+/* One AdamW step on n parameters with step count t >= 1 (bias corrections
+ * 1 / (1 - beta^t)); m and v are the moment buffers (zero at t = 1). */
+int hn_mlp_adamw(float *params, const float *grads, float *m, float *v, int64_t n, int32_t t,
+                 const hn_adamw_opts *opts, void *stream);
+
+/* Train in place: `epochs` passes over (x [n][128], labels [n]) in order, in
+ * batches of `batch` (the last one ragged), one AdamW step per batch with
+ * fresh moments.  losses: NULL or float [epochs * ceil(n / batch)], the mean
+ * loss of every step. */
+int hn_seed_train(float *params, const float *x, const int32_t *labels, int64_t n,
+                  int32_t batch, int32_t epochs, const hn_adamw_opts *opts, float *losses,
+                  void *stream);
+
+/* k-means++ D^2 seeding over the index rows (no Lloyd iterations):
+ * anchors[0] = floor(u[0] n) (n - 1 if that is n); for t >= 1, with
+ * D(x) = min over chosen anchors a of 2 - 2 sim(a, x) and integer weights
+ * w(x) = floor(max(0, D(x)) 2^30), anchors[t] is the first entry whose
+ * running weight sum exceeds floor(u[t] * total) (n - 1 if none).
+ *   u        double [n_anchor], uniform draws in [0, 1) (the caller's random
+ *            numbers).
+ *   anchors  int64 [n_anchor].  Exact integer arithmetic: deterministic. */
+int hn_kmeanspp(const hn_index *ix, int32_t n_anchor, const double *u, int64_t *anchors,
+                void *stream);
+
+/* Training labels: labels[i] = the a in [0, n_anchor) maximising
+ * sim(x_nn(i), x_anchors[a]) (ties to the smaller a), where nn(i) is query
+ * i's exact top-1 (hn_search_top1); -1 for a query with a non-finite
+ * component.  Anchors are checked to be entries (synchronises). */
+int hn_seed_labels(const hn_index *ix, const int64_t *anchors, int32_t n_anchor,
+                   const float *queries, int64_t q, int32_t *labels, void *stream);
+
+/* Install a seed model in the index for HN_SEED_LEARNED: the parameters are
+ * copied (weights rounded to bf16), anchors int64 [n_anchor] with n_anchor =
+ * HN_MLP_OUT, each an entry of the index.  Replaces an earlier model;
+ * synchronises `stream`. */
+int hn_set_seed_model(hn_index *ix, const float *params, const int64_t *anchors,
+                      int32_t n_anchor, void *stream);
 
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *hn_last_error(void);

@@ -10,14 +10,17 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (HN_BUILD_LOW_PRECISION, HN_BUILD_NO_VALIDATE, HN_PREC_BF16,
-                   HN_PREC_FP8, HN_PREC_FP32, HN_SEED_LEARNED, HN_SEED_PLAIN, HNError)
+from ._lib import (HN_BUILD_LOW_PRECISION, HN_BUILD_NO_VALIDATE, HN_MLP_PARAMS, HN_PREC_BF16,
+                   HN_PREC_FP8, HN_PREC_FP32, HN_SEED_LEARNED, HN_SEED_PLAIN, HN_SEED_WINDOW,
+                   HNError)
 
-__all__ = ["Index", "bruteforce_top1", "profile", "HNError", "PRECISIONS", "HN_PREC_FP32",
-           "HN_PREC_BF16", "HN_PREC_FP8", "HN_SEED_PLAIN", "HN_SEED_LEARNED",
-           "HN_BUILD_NO_VALIDATE", "HN_BUILD_LOW_PRECISION"]
+__all__ = ["Index", "bruteforce_top1", "profile", "HNError", "PRECISIONS", "SEEDS",
+           "HN_PREC_FP32", "HN_PREC_BF16", "HN_PREC_FP8", "HN_SEED_PLAIN", "HN_SEED_LEARNED",
+           "HN_SEED_WINDOW", "HN_BUILD_NO_VALIDATE", "HN_BUILD_LOW_PRECISION", "HN_MLP_PARAMS",
+           "mlp_forward", "mlp_grad", "mlp_adamw", "seed_train"]
 
 PRECISIONS = {"fp32": HN_PREC_FP32, "bf16": HN_PREC_BF16, "fp8": HN_PREC_FP8}
+SEEDS = {"plain": HN_SEED_PLAIN, "learned": HN_SEED_LEARNED, "window": HN_SEED_WINDOW}
 
 
 def _torch():
@@ -52,7 +55,7 @@ def _opts(precision="fp32", query_tiles=0, chunk_blocks=0, survivor_cap=0, beta=
           seed="plain"):
     o = _lib.SearchOpts()
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    o.seed = {"plain": HN_SEED_PLAIN, "learned": HN_SEED_LEARNED}[seed] if isinstance(seed, str) else int(seed)
+    o.seed = SEEDS[seed] if isinstance(seed, str) else int(seed)
     o.query_tiles = int(query_tiles)
     o.chunk_blocks = int(chunk_blocks)
     o.survivor_cap = int(survivor_cap)
@@ -95,7 +98,8 @@ class Index:
         return {"n": n.value, "k": k.value, "alpha": a.value, "norms": tuple(norms)}
 
     def search(self, queries, precision="fp32", query_tiles=0, chunk_blocks=0,
-               survivor_cap=0, beta=None, aux=False, stats=False, stream=None, out=None):
+               survivor_cap=0, beta=None, aux=False, stats=False, stream=None, out=None,
+               seed="plain"):
         """Exact top-1 per query: (idx int64 [q], sim float64 [q]) plus the
         auxiliary outputs (dict) and/or the call's stats when requested."""
         torch = _torch()
@@ -106,7 +110,7 @@ class Index:
             sim = torch.empty(q, dtype=torch.float64, device=queries.device)
         else:
             idx, sim = out
-        o = _opts(precision, query_tiles, chunk_blocks, survivor_cap, beta)
+        o = _opts(precision, query_tiles, chunk_blocks, survivor_cap, beta, seed)
         a = None
         auxd = None
         if aux:
@@ -153,6 +157,94 @@ class Index:
         p = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         _lib.check(_lib.lib().hn_scan_scores(self._h, qp, q, p, _ptr(out), _stream(stream)))
         return out
+
+
+    def kmeanspp(self, n_anchor, u, stream=None):
+        """k-means++ D^2 seeding (hn_kmeanspp): int64 [n_anchor] entry ids
+        from the uniform draws u (float64 [n_anchor], device)."""
+        torch = _torch()
+        up = _dev(u, torch.float64, "u", 1)
+        if u.shape[0] < n_anchor:
+            raise ValueError("u needs n_anchor draws")
+        out = torch.empty(int(n_anchor), dtype=torch.int64, device=u.device)
+        _lib.check(_lib.lib().hn_kmeanspp(self._h, int(n_anchor), up, _ptr(out),
+                                          _stream(stream)))
+        return out
+
+    def seed_labels(self, anchors, queries, stream=None):
+        """Training labels (hn_seed_labels): int32 [q]."""
+        torch = _torch()
+        ap = _dev(anchors, torch.int64, "anchors", 1)
+        qp = _dev(queries, torch.float32, "queries", 2)
+        out = torch.empty(queries.shape[0], dtype=torch.int32, device=queries.device)
+        _lib.check(_lib.lib().hn_seed_labels(self._h, ap, anchors.shape[0], qp,
+                                             queries.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def set_seed_model(self, params, anchors, stream=None):
+        """Install the seed model (hn_set_seed_model) for seed="learned"."""
+        torch = _torch()
+        pp = _dev(params, torch.float32, "params", 1)
+        if params.shape[0] != HN_MLP_PARAMS:
+            raise ValueError("params must hold %d values" % HN_MLP_PARAMS)
+        ap = _dev(anchors, torch.int64, "anchors", 1)
+        _lib.check(_lib.lib().hn_set_seed_model(self._h, pp, ap, anchors.shape[0],
+                                                _stream(stream)))
+
+
+def _adamw(lr, beta1, beta2, eps, weight_decay):
+    return _lib.AdamWOpts(float(lr), float(beta1), float(beta2), float(eps), float(weight_decay))
+
+
+def mlp_forward(params, x, stream=None):
+    """Seed-model logits [b][512] (hn_mlp_forward)."""
+    torch = _torch()
+    pp = _dev(params, torch.float32, "params", 1)
+    xp = _dev(x, torch.float32, "x", 2)
+    out = torch.empty((x.shape[0], 512), dtype=torch.float32, device=x.device)
+    _lib.check(_lib.lib().hn_mlp_forward(pp, xp, x.shape[0], _ptr(out), _stream(stream)))
+    return out
+
+
+def mlp_grad(params, x, labels, stream=None):
+    """(grads float32 [HN_MLP_PARAMS], mean loss float32 [1]) (hn_mlp_grad)."""
+    torch = _torch()
+    pp = _dev(params, torch.float32, "params", 1)
+    xp = _dev(x, torch.float32, "x", 2)
+    lp = _dev(labels, torch.int32, "labels", 1)
+    grads = torch.empty(HN_MLP_PARAMS, dtype=torch.float32, device=x.device)
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    _lib.check(_lib.lib().hn_mlp_grad(pp, xp, lp, x.shape[0], _ptr(grads), _ptr(loss),
+                                      _stream(stream)))
+    return grads, loss
+
+
+def mlp_adamw(params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0,
+              stream=None):
+    """One in-place AdamW step (hn_mlp_adamw)."""
+    torch = _torch()
+    o = _adamw(lr, beta1, beta2, eps, weight_decay)
+    n = params.shape[0]
+    _lib.check(_lib.lib().hn_mlp_adamw(
+        _dev(params, torch.float32, "params", 1), _dev(grads, torch.float32, "grads", 1),
+        _dev(m, torch.float32, "m", 1), _dev(v, torch.float32, "v", 1), n, int(t),
+        ctypes.byref(o), _stream(stream)))
+
+
+def seed_train(params, x, labels, batch, epochs, lr, beta1=0.9, beta2=0.999, eps=1e-8,
+               weight_decay=0.0, stream=None):
+    """Train the seed model in place (hn_seed_train); returns the per-step
+    mean losses (float32 tensor)."""
+    torch = _torch()
+    n = x.shape[0]
+    steps = int(epochs) * ((n + int(batch) - 1) // int(batch))
+    losses = torch.empty(max(steps, 1), dtype=torch.float32, device=x.device)
+    o = _adamw(lr, beta1, beta2, eps, weight_decay)
+    _lib.check(_lib.lib().hn_seed_train(
+        _dev(params, torch.float32, "params", 1), _dev(x, torch.float32, "x", 2),
+        _dev(labels, torch.int32, "labels", 1), n, int(batch), int(epochs), ctypes.byref(o),
+        _ptr(losses), _stream(stream)))
+    return losses[:steps]
 
 
 class profile:

@@ -19,7 +19,8 @@ HN_ERR_DEVICE = -4
 HN_ERR_UNSUPPORTED = -5
 
 HN_PREC_FP32, HN_PREC_BF16, HN_PREC_FP8 = 0, 1, 2
-HN_SEED_PLAIN, HN_SEED_LEARNED = 0, 1
+HN_SEED_PLAIN, HN_SEED_LEARNED, HN_SEED_WINDOW = 0, 1, 2
+HN_MLP_IN, HN_MLP_H, HN_MLP_OUT, HN_MLP_PARAMS = 128, 256, 512, 230400
 HN_BUILD_NO_VALIDATE = 1 << 0
 HN_BUILD_LOW_PRECISION = 1 << 1
 
@@ -44,6 +45,11 @@ class SearchStats(ctypes.Structure):
     _fields_ = [("survivors", _i64), ("overflow_queries", _i64)]
 
 
+class AdamWOpts(ctypes.Structure):
+    _fields_ = [("lr", _dbl), ("beta1", _dbl), ("beta2", _dbl), ("eps", _dbl),
+                ("weight_decay", _dbl)]
+
+
 class HNError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("hnsearch error %d: %s" % (code, msg))
@@ -65,6 +71,14 @@ SIGNATURES = {
     "hn_profile_begin": (_i32, [_vp]),
     "hn_profile_end": (_i32, [_vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_dbl),
                               ctypes.POINTER(_i64), _i32, ctypes.POINTER(_i32)]),
+    "hn_mlp_forward": (_i32, [_vp, _vp, _i64, _vp, _vp]),
+    "hn_mlp_grad": (_i32, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "hn_mlp_adamw": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, ctypes.POINTER(AdamWOpts), _vp]),
+    "hn_seed_train": (_i32, [_vp, _vp, _vp, _i64, _i32, _i32, ctypes.POINTER(AdamWOpts), _vp,
+                             _vp]),
+    "hn_kmeanspp": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "hn_seed_labels": (_i32, [_vp, _vp, _i32, _vp, _i64, _vp, _vp]),
+    "hn_set_seed_model": (_i32, [_vp, _vp, _vp, _i32, _vp]),
     "hn_last_error": (ctypes.c_char_p, []),
 }
 

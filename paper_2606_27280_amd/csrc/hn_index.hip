@@ -30,22 +30,25 @@ namespace {
 struct ArenaKey {
     int device;
     void *stream;
-    bool operator==(const ArenaKey &o) const { return device == o.device && stream == o.stream; }
+    int slot;
+    bool operator==(const ArenaKey &o) const {
+        return device == o.device && stream == o.stream && slot == o.slot;
+    }
 };
 struct ArenaKeyHash {
     size_t operator()(const ArenaKey &k) const {
-        return std::hash<void *>()(k.stream) * 31u + (size_t)k.device;
+        return (std::hash<void *>()(k.stream) * 31u + (size_t)k.device) * 7u + (size_t)k.slot;
     }
 };
 std::mutex g_arena_mu;
 std::unordered_map<ArenaKey, Arena *, ArenaKeyHash> g_arenas;
 }  // namespace
 
-int arena_for(void *stream, size_t bytes, Arena **out) {
+int arena_for(void *stream, size_t bytes, Arena **out, int slot) {
     int dev = 0;
     HN_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_arena_mu);
-    Arena *&a = g_arenas[ArenaKey{dev, stream}];
+    Arena *&a = g_arenas[ArenaKey{dev, stream, slot}];
     if (!a) a = new (std::nothrow) Arena();
     if (!a) return fail(HN_ERR_OOM, "host allocation failed");
     if (a->cap < bytes) {
@@ -242,6 +245,9 @@ void free_index(hn_index *ix) {
     if (ix->major32) (void)hipFree(ix->major32);
     if (ix->major16) (void)hipFree(ix->major16);
     if (ix->major8) (void)hipFree(ix->major8);
+    if (ix->seed_w) (void)hipFree(ix->seed_w);
+    if (ix->seed_b) (void)hipFree(ix->seed_b);
+    if (ix->seed_anchor) (void)hipFree(ix->seed_anchor);
     delete ix;
 }
 

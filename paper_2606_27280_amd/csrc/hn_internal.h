@@ -48,8 +48,10 @@ struct Arena {
     }
 };
 // Reserve `bytes` of scratch for `stream` (device of the caller).  Returns
-// HN_OK and an arena whose `used` is 0.
-int arena_for(void *stream, size_t bytes, Arena **out);
+// HN_OK and an arena whose `used` is 0.  Slots are independent arenas of the
+// same stream: the search uses slot 0, the seed-model code slot 1 (so a seed
+// step can run a search and keep its own buffers).
+int arena_for(void *stream, size_t bytes, Arena **out, int slot = 0);
 
 // Brackets the kernels launched in its scope with HIP events when a profile
 // session is open on the stream (hn_profile_begin); otherwise does nothing.
@@ -134,6 +136,11 @@ __host__ __device__ __forceinline__ double gamma_n(int n, double u) {
     return (double)n * u / (1.0 - (double)n * u);
 }
 
+// The search's learned-seed stage: per query, L (lower) and its entry
+// (lower_idx) from the index's seed model.
+int learned_seed(const hn_index *ix, const float *queries, int64_t q, double *lower,
+                 int64_t *lower_idx, hipStream_t s);
+
 }  // namespace hn
 
 // The index (opaque to callers).
@@ -155,4 +162,10 @@ struct hn_index {
     float scale8 = 1.0f;         // power-of-two scale of the fp8 copy
     double mu_major8 = 0;        // max ||scale8 * fp8(x[:k])||, rounded up
     double res8 = 0;             // max ||scale8 * fp8(x[:k]) - x[:k]||, rounded up
+    // learned seed model (hn_set_seed_model): bf16 weights W1 | W2 | W3,
+    // float32 biases b1 | b2 | b3, anchor entry ids
+    uint16_t *seed_w = nullptr;
+    float *seed_b = nullptr;
+    int32_t *seed_anchor = nullptr;
+    int32_t n_anchor = 0;
 };

@@ -722,9 +722,9 @@ inline void launch_cfgs(int cfg, const Plan &p, const ScanArgs &A, hipStream_t s
 }
 
 // Instantiated modes: argmax and filter for every tile and configuration;
-// store (the score buffer) for configuration 0; the window mode only for the
-// 128-wide float32 tile of the exhaustive scan.  Returns nonzero if the
-// requested combination is not compiled.
+// store (the score buffer) for configuration 0; the window mode (the
+// single-pass forms and the exhaustive scan) where the tile family asks for it.
+// Returns nonzero if the requested combination is not compiled.
 template <class Tile, bool Window>
 inline int launch_tile(int mode, int cfg, const Plan &p, const ScanArgs &A, hipStream_t s) {
     if (cfg < 0 || cfg >= kNumCfg || kCfgNQ[cfg] * tile_cost<Tile>() > kTileBudget) return 1;

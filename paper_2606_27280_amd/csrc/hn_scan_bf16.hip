@@ -5,10 +5,10 @@
 namespace hn {
 int launch_scan_bf16(int mode, int w, int cfg, const Plan &p, const ScanArgs &A, hipStream_t s) {
     switch (w) {
-        case 16: return launch_tile<BF16Tile32<16>, false>(mode, cfg, p, A, s);
-        case 32: return launch_tile<BF16Tile32<32>, false>(mode, cfg, p, A, s);
-        case 64: return launch_tile<BF16Tile<64>, false>(mode, cfg, p, A, s);
-        case 128: return launch_tile<BF16Tile<128>, false>(mode, cfg, p, A, s);
+        case 16: return launch_tile<BF16Tile32<16>, true>(mode, cfg, p, A, s);
+        case 32: return launch_tile<BF16Tile32<32>, true>(mode, cfg, p, A, s);
+        case 64: return launch_tile<BF16Tile<64>, true>(mode, cfg, p, A, s);
+        case 128: return launch_tile<BF16Tile<128>, true>(mode, cfg, p, A, s);
     }
     return 1;
 }

@@ -6,10 +6,10 @@ namespace hn {
 int launch_scan_f32_narrow(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
                            hipStream_t s) {
     switch (w) {
-        case 4: return launch_tile<F32Tile32<4>, false>(mode, cfg, p, A, s);
-        case 8: return launch_tile<F32Tile32<8>, false>(mode, cfg, p, A, s);
-        case 16: return launch_tile<F32Tile32<16>, false>(mode, cfg, p, A, s);
-        case 32: return launch_tile<F32Tile32<32>, false>(mode, cfg, p, A, s);
+        case 4: return launch_tile<F32Tile32<4>, true>(mode, cfg, p, A, s);
+        case 8: return launch_tile<F32Tile32<8>, true>(mode, cfg, p, A, s);
+        case 16: return launch_tile<F32Tile32<16>, true>(mode, cfg, p, A, s);
+        case 32: return launch_tile<F32Tile32<32>, true>(mode, cfg, p, A, s);
     }
     return 1;
 }

@@ -6,7 +6,7 @@ namespace hn {
 int launch_scan_f32_wide(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
                          hipStream_t s) {
     switch (w) {
-        case 64: return launch_tile<F32Tile<64>, false>(mode, cfg, p, A, s);
+        case 64: return launch_tile<F32Tile<64>, true>(mode, cfg, p, A, s);
         case 128: return launch_tile<F32Tile<128>, true>(mode, cfg, p, A, s);
     }
     return 1;

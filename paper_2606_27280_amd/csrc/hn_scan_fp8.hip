@@ -5,8 +5,8 @@
 namespace hn {
 int launch_scan_fp8(int mode, int w, int cfg, const Plan &p, const ScanArgs &A, hipStream_t s) {
     switch (w) {
-        case 16: return launch_tile<FP8Tile32<16>, false>(mode, cfg, p, A, s);
-        case 32: return launch_tile<FP8Tile32<32>, false>(mode, cfg, p, A, s);
+        case 16: return launch_tile<FP8Tile32<16>, true>(mode, cfg, p, A, s);
+        case 32: return launch_tile<FP8Tile32<32>, true>(mode, cfg, p, A, s);
     }
     return 1;
 }

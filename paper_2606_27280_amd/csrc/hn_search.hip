@@ -135,7 +135,14 @@ struct SeedArgs {
     int fp8;       // residuals of the fp8 operands; thresholds in scan units
     double res_mu, res_x, res_acc_rel;
     double scale_x;  // fp8: power-of-two scale of the entry copy
-    const double *lower;  // given L (filter-only); NULL: plain seed
+    const double *lower;  // given L (filter-only, learned or no seed); NULL: plain seed
+    const int64_t *lower_idx;  // entry of each given L, or NULL (none)
+    // single-pass window (NULL: none): exact width 2 (beta + eps_q) in scan
+    // units, the float width the scan subtracts (widened for its rounding),
+    // and the scan's starting running maximum T_q + width
+    double *win;
+    float *win_scan, *init_best;
+    double bound_mu;  // max norm of the scanned entry copy (bounds |s~|)
     const QNorm *qn;
     float *thr;           // [q_pad]: scan threshold T_q (+inf for padding)
     float *thr32;         // [q]: float32 re-check threshold, or NULL
@@ -168,7 +175,13 @@ __global__ __launch_bounds__(256) void seed_kernel(SeedArgs S) {
     if (i == 0 && lane == 0) *S.counter = 0;
     if (i >= S.q_pad) return;
     if (i >= S.q) {
-        if (lane == 0) S.thr[i] = INFINITY;
+        if (lane == 0) {
+            S.thr[i] = INFINITY;
+            if (S.win_scan) {
+                S.win_scan[i] = 0.0f;
+                S.init_best[i] = -INFINITY;
+            }
+        }
         return;
     }
     const QNorm qn = S.qn[i];
@@ -183,6 +196,11 @@ __global__ __launch_bounds__(256) void seed_kernel(SeedArgs S) {
             S.seed_sim[i] = NAN;
             S.slack[i] = NAN;
             S.best_key[i] = 0;
+            if (S.win_scan) {
+                S.win[i] = 0.0;
+                S.win_scan[i] = 0.0f;
+                S.init_best[i] = INFINITY;
+            }
         }
         return;
     }
@@ -191,6 +209,7 @@ __global__ __launch_bounds__(256) void seed_kernel(SeedArgs S) {
     int64_t b = -1;
     if (S.lower) {
         L = S.lower[i];
+        b = S.lower_idx ? S.lower_idx[i] : -1;
     } else {
         float bv = -INFINITY;
         int bi = -1;
@@ -242,6 +261,15 @@ __global__ __launch_bounds__(256) void seed_kernel(SeedArgs S) {
     // the threshold in scan units is the same bound divided by s_q s_x, exact
     const double unit = S.fp8 ? 1.0 / ((double)qn.sc8 * S.scale_x) : 1.0;
     S.thr[i] = round_down_f32((L - S.beta - eps) * unit);
+    if (S.win_scan) {
+        // |s~| <= (||q_M|| + r_q) max ||x^_M|| (1 + 2^-20), in scan units
+        const double rq = S.fp8 ? qn.res8 : (S.scan_res ? qn.res16 : 0.0);
+        const double bound = (qn.major + rq) * S.bound_mu * unit * (1.0 + ldexp(1.0, -20));
+        const double w = 2.0 * (S.beta + eps) * unit;
+        S.win[i] = w;
+        S.win_scan[i] = __double2float_ru(w + ldexp(1.0, -21) * (bound + w));
+        S.init_best[i] = round_down_f32((L - S.beta - eps) * unit + w);
+    }
     if (S.thr32) {
         double e32 = gamma_n(S.k, kU32) * qn.major * S.mu_major + S.k * ldexp(1.0, -125);
         double eps32 = (e32 + en + e64) * (1.0 + ldexp(1.0, -30)) + ldexp(1.0, -40);
@@ -498,6 +526,25 @@ __global__ __launch_bounds__(256) void bf_threshold(const float *part_val, int32
     thr[i] = __double2float_rd((double)m - win[i]);
 }
 
+// Single-pass re-filter threshold: max(T_q, m - w_q) with m the final scan
+// maximum over all chunks (which includes the starting value T_q + w_q).
+__global__ __launch_bounds__(256) void win_threshold(const float *part_val, int32_t n_chunks,
+                                                     int32_t q_pad, int64_t q, const double *win,
+                                                     const float *thr, float *out) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= q) return;
+    float m = -INFINITY;
+    for (int c = 0; c < n_chunks; ++c) m = fmaxf(m, part_val[(int64_t)c * q_pad + i]);
+    out[i] = fmaxf(thr[i], __double2float_rd((double)m - win[i]));
+}
+
+__global__ void fill_lower(double *lower, int64_t *idx, int64_t q) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < q; i += (int64_t)gridDim.x * 256) {
+        lower[i] = -INFINITY;
+        idx[i] = -1;
+    }
+}
+
 // ---------------------------------------------------------- launch helpers
 
 unsigned blocks_for(int64_t items, int per = 256) {
@@ -558,6 +605,11 @@ struct Work {
     unsigned *work = nullptr;  // kWorkWords scan counters (see kWorkWords)
     int *redo = nullptr;       // [n_items] items to re-run
     int64_t cap = 0;
+    // single-pass forms
+    double *win = nullptr;
+    float *win_scan = nullptr, *init_best = nullptr, *thr_ref = nullptr, *pair_val = nullptr;
+    double *lower = nullptr;
+    int64_t *lower_idx = nullptr;
 };
 
 // The scan stream and query operands of a precision.
@@ -606,7 +658,10 @@ int validate_opts(const hn_index *ix, const hn_search_opts *o) {
     if (!o) return HN_OK;
     int rc = check_precision(ix, o->precision);
     if (rc) return rc;
-    if (o->seed != HN_SEED_PLAIN) return fail(HN_ERR_UNSUPPORTED, "seed %d is not available", o->seed);
+    if (o->seed != HN_SEED_PLAIN && o->seed != HN_SEED_LEARNED && o->seed != HN_SEED_WINDOW)
+        return fail(HN_ERR_INVALID_ARG, "seed %d is not a seed mode", o->seed);
+    if (o->seed == HN_SEED_LEARNED && !ix->seed_w)
+        return fail(HN_ERR_INVALID_ARG, "the learned seed needs a model (hn_set_seed_model)");
     if (o->query_tiles != 0 && o->query_tiles != 1 && o->query_tiles != 2 && o->query_tiles != 4 &&
         o->query_tiles != 8)
         return fail(HN_ERR_INVALID_ARG, "query_tiles must be 0, 1, 2, 4 or 8");
@@ -618,9 +673,12 @@ int validate_opts(const hn_index *ix, const hn_search_opts *o) {
 }
 
 // Prepare queries, run the plain-seed pass and compute thresholds.  With
-// `lower` the seed pass is skipped and L is taken from the caller.
+// `lower` the seed pass is skipped and L (and its entry, lower_idx, if not
+// NULL) is taken from the caller.  `window`: also the single-pass window
+// (W.win, W.win_scan, W.init_best) and the pair values.
 int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_search_opts &o,
-               const double *lower, int64_t cap, Work &W, hipStream_t s) {
+               const double *lower, const int64_t *lower_idx, int64_t cap, Work &W,
+               hipStream_t s, bool window = false) {
     W.precision = o.precision;
     W.width = stream_width(ix, W.precision);
     W.stream_x = stream_of(ix, W.precision);
@@ -656,6 +714,15 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     add(p.n_items, 4);
     add(cap, sizeof(int2));
     add(cap, 8);
+    if (window) {
+        add(p.q_pad, 8);
+        add(p.q_pad, 4);
+        add(p.q_pad, 4);
+        add(q, 4);
+        add(cap, 4);
+        add(q, 8);
+        add(q, 8);
+    }
     Arena *ar = nullptr;
     int rc = arena_for((void *)s, bytes, &ar);
     if (rc) return rc;
@@ -680,9 +747,29 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     W.redo = ar->take<int>(p.n_items);
     W.pairs = ar->take<int2>(cap);
     W.psim = ar->take<double>(cap);
+    if (window) {
+        W.win = ar->take<double>(p.q_pad);
+        W.win_scan = ar->take<float>(p.q_pad);
+        W.init_best = ar->take<float>(p.q_pad);
+        W.thr_ref = ar->take<float>(q);
+        W.pair_val = ar->take<float>(cap);
+        W.lower = ar->take<double>(q);
+        W.lower_idx = ar->take<int64_t>(q);
+    }
 
     launch_prep(ix, queries, q, p, W, s);
     HN_HIP(hipGetLastError());
+    if (window) {
+        if (o.seed == HN_SEED_LEARNED) {
+            rc = learned_seed(ix, queries, q, W.lower, W.lower_idx, s);
+            if (rc) return rc;
+        } else {
+            hipLaunchKernelGGL(fill_lower, dim3(blocks_for(q)), dim3(256), 0, s, W.lower,
+                               W.lower_idx, q);
+        }
+        lower = W.lower;
+        lower_idx = W.lower_idx;
+    }
 
     ScanArgs A;
     memset(&A, 0, sizeof A);
@@ -757,6 +844,15 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
         S.res_acc_rel = gamma_n(ix->k, kU32);
     }
     S.lower = lower;
+    S.lower_idx = lower_idx;
+    if (window) {
+        S.win = W.win;
+        S.win_scan = W.win_scan;
+        S.init_best = W.init_best;
+        S.bound_mu = W.precision == HN_PREC_FP32   ? ix->mu_major
+                     : W.precision == HN_PREC_BF16 ? ix->mu_major16
+                                                   : ix->mu_major8;
+    }
     S.qn = W.qn;
     S.thr = W.thr;
     S.thr32 = W.precision == HN_PREC_FP32 ? nullptr : W.thr32;
@@ -821,29 +917,45 @@ int64_t default_cap(int64_t n, int64_t q) {
 
 using namespace hn;
 
-extern "C" int hn_search_top1(const hn_index *ix, const float *queries, int64_t q,
-                              int64_t *out_idx, double *out_sim, const hn_search_opts *opts,
-                              const hn_search_aux *aux, hn_search_stats *stats, void *stream) {
-    clear_error();
-    if (!ix) return fail(HN_ERR_INVALID_ARG, "null index");
-    if (q < 0) return fail(HN_ERR_INVALID_ARG, "q must be >= 0");
-    if (q >= ((int64_t)1 << 31) - 4096) return fail(HN_ERR_UNSUPPORTED, "q must be < 2^31");
-    if (q > 0 && (!queries || !out_idx || !out_sim))
-        return fail(HN_ERR_INVALID_ARG, "null queries or outputs");
-    int rc = validate_opts(ix, opts);
-    if (rc) return rc;
-    if (stats) memset(stats, 0, sizeof *stats);
-    if (q == 0) return HN_OK;
-    hn_search_opts o = opts ? *opts : hn_search_opts{HN_PREC_FP32, HN_SEED_PLAIN, 0, 0, 0, -1.0};
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t cap = o.survivor_cap > 0 ? o.survivor_cap : default_cap(ix->n, q);
+namespace hn {
+namespace {
 
+// Survivor-list budget per query of the single-pass forms (the window keeps
+// more pairs than the two-pass threshold) and the query batch that fits it.
+int64_t window_per_query(int64_t n) { return std::max<int64_t>(8192, n / 32); }
+int64_t window_batch(int64_t n) {
+    return std::max<int64_t>(256, ((int64_t)1 << 29) / window_per_query(n));
+}
+
+// One batch of queries through the whole pipeline.
+int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *out_idx,
+                 double *out_sim, const hn_search_opts &o, const hn_search_aux *aux,
+                 hn_search_stats *stats, hipStream_t s) {
+    const bool single = o.seed != HN_SEED_PLAIN;
+    const int64_t cap =
+        o.survivor_cap > 0
+            ? o.survivor_cap
+            : (single ? std::min<int64_t>(std::max<int64_t>(q * window_per_query(ix->n), 1 << 20),
+                                          (int64_t)1 << 29)
+                      : default_cap(ix->n, q));
     Work W;
-    rc = stage_seed(ix, queries, q, o, nullptr, cap, W, s);
+    int rc = stage_seed(ix, queries, q, o, nullptr, nullptr, cap, W, s, single);
     if (rc) return rc;
     ScanArgs A = filter_args(ix, W, q, W.pairs, cap);
-    rc = launch_scan<kFilter>(W.precision, W.width, W.cfg, W.plan, A, s);
-    if (rc) return rc;
+    if (single) {
+        A.thr = W.win_scan;
+        A.init_best = W.init_best;
+        A.pair_val = W.pair_val;
+        A.part_val = W.part_val;
+        rc = launch_scan<kWindow>(W.precision, W.width, W.cfg, W.plan, A, s);
+        if (rc) return rc;
+        ProfScope prof_(s, "win_threshold");
+        hipLaunchKernelGGL(win_threshold, dim3(blocks_for(q)), dim3(256), 0, s, W.part_val,
+                           W.plan.n_chunks, (int32_t)W.plan.q_pad, q, W.win, W.thr, W.thr_ref);
+    } else {
+        rc = launch_scan<kFilter>(W.precision, W.width, W.cfg, W.plan, A, s);
+        if (rc) return rc;
+    }
 
     RescoreArgs R;
     memset(&R, 0, sizeof R);
@@ -865,7 +977,12 @@ extern "C" int hn_search_top1(const hn_index *ix, const float *queries, int64_t 
     R.q = q;
     R.count = (aux && aux->survivors) || stats;
     const unsigned rgrid = 2048;
-    if (W.precision == HN_PREC_FP32) {
+    if (single) {
+        R.pair_val = W.pair_val;
+        R.thr32 = W.thr_ref;
+        ProfScope prof_(s, "rescore_window");
+        hipLaunchKernelGGL(rescore_kernel<2>, dim3(rgrid), dim3(256), 0, s, R);
+    } else if (W.precision == HN_PREC_FP32) {
         ProfScope prof_(s, "rescore");
         hipLaunchKernelGGL(rescore_kernel<0>, dim3(rgrid), dim3(256), 0, s, R);
     } else {
@@ -934,6 +1051,49 @@ extern "C" int hn_search_top1(const hn_index *ix, const float *queries, int64_t 
     return HN_OK;
 }
 
+}  // namespace
+}  // namespace hn
+
+extern "C" int hn_search_top1(const hn_index *ix, const float *queries, int64_t q,
+                              int64_t *out_idx, double *out_sim, const hn_search_opts *opts,
+                              const hn_search_aux *aux, hn_search_stats *stats, void *stream) {
+    clear_error();
+    if (!ix) return fail(HN_ERR_INVALID_ARG, "null index");
+    if (q < 0) return fail(HN_ERR_INVALID_ARG, "q must be >= 0");
+    if (q >= ((int64_t)1 << 31) - 4096) return fail(HN_ERR_UNSUPPORTED, "q must be < 2^31");
+    if (q > 0 && (!queries || !out_idx || !out_sim))
+        return fail(HN_ERR_INVALID_ARG, "null queries or outputs");
+    int rc = validate_opts(ix, opts);
+    if (rc) return rc;
+    if (stats) memset(stats, 0, sizeof *stats);
+    if (q == 0) return HN_OK;
+    const hn_search_opts o =
+        opts ? *opts : hn_search_opts{HN_PREC_FP32, HN_SEED_PLAIN, 0, 0, 0, -1.0};
+    hipStream_t s = (hipStream_t)stream;
+    // the single-pass forms run in query batches that bound the pair list
+    const int64_t qb = o.seed == HN_SEED_PLAIN ? q : window_batch(ix->n);
+    for (int64_t q0 = 0; q0 < q; q0 += qb) {
+        const int64_t nb = std::min<int64_t>(qb, q - q0);
+        hn_search_aux a2;
+        if (aux) {
+            a2.seed_idx = aux->seed_idx ? aux->seed_idx + q0 : nullptr;
+            a2.seed_sim = aux->seed_sim ? aux->seed_sim + q0 : nullptr;
+            a2.threshold = aux->threshold ? aux->threshold + q0 : nullptr;
+            a2.survivors = aux->survivors ? aux->survivors + q0 : nullptr;
+            a2.slack = aux->slack ? aux->slack + q0 : nullptr;
+        }
+        hn_search_stats st{0, 0};
+        rc = search_batch(ix, queries + q0 * kDim, nb, out_idx + q0, out_sim + q0, o,
+                          aux ? &a2 : nullptr, stats ? &st : nullptr, s);
+        if (rc) return rc;
+        if (stats) {
+            stats->survivors += st.survivors;
+            stats->overflow_queries += st.overflow_queries;
+        }
+    }
+    return HN_OK;
+}
+
 extern "C" int hn_filter_survivors(const hn_index *ix, const float *queries, int64_t q,
                                    const double *lower, int32_t *pairs, int64_t cap,
                                    int64_t *count, double *slack, const hn_search_opts *opts,
@@ -951,7 +1111,7 @@ extern "C" int hn_filter_survivors(const hn_index *ix, const float *queries, int
     hn_search_opts o = opts ? *opts : hn_search_opts{HN_PREC_FP32, HN_SEED_PLAIN, 0, 0, 0, -1.0};
     hipStream_t s = (hipStream_t)stream;
     Work W;
-    rc = stage_seed(ix, queries, q, o, lower, 1, W, s);
+    rc = stage_seed(ix, queries, q, o, lower, nullptr, 1, W, s);
     if (rc) return rc;
     ScanArgs A = filter_args(ix, W, q, reinterpret_cast<int2 *>(pairs), cap);
     rc = launch_scan<kFilter>(W.precision, W.width, W.cfg, W.plan, A, s);
