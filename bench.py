@@ -10,6 +10,12 @@ Prints one JSON line with the throughput, the GPU brute-force baseline on the
 same queries, the pruned fraction, the dominant kernel's roofline fraction
 (kernel time from HIP events recorded on the library's stream during the
 timed steps) and the CPU oracle timed on a bounded sample.
+
+Other workloads: --workload 3 (N = 4M, K = 8, alpha = 1/32, Q = 65,536; the
+precision form) and --workload 5 (N = 4M, K = 16, alpha = 1/8, Q = 65,536
+held-out queries; the seed model is built first, untimed: k-means++ anchors,
+labels of 200,000 training queries, training; then the plain two-pass seed,
+the learned single pass and the window-only single pass are all timed).
 """
 import argparse
 import json
@@ -28,6 +34,9 @@ PEAK = {  # MI355X published dense peaks
     "bf16_mfma_tflops": 2500.0,
     "fp8_mfma_tflops": 5000.0,
 }
+
+
+ARGS = None
 
 
 def log(*a):
@@ -49,7 +58,49 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--query-tiles", type=int, default=0)
     ap.add_argument("--chunk-blocks", type=int, default=0)
+    ap.add_argument("--seed", default=None, choices=["plain", "learned", "window"],
+                    help="timed seed form (default: learned for workload 5, else plain)")
+    ap.add_argument("--epochs", type=int, default=4, help="seed-model training epochs")
+    ap.add_argument("--batch", type=int, default=1024, help="seed-model training batch")
+    ap.add_argument("--lr", type=float, default=2e-3)
     return ap.parse_args()
+
+
+def build_seed_model(hn, ix, w, db, dev, torch):
+    """Anchors (k-means++), labels (exact GPU search), training, install.
+    Returns a report dict with the time of each step."""
+    import hn_inputs
+    rep = {}
+    t0 = time.perf_counter()
+    u = torch.from_numpy(hn_inputs.uniform_draws(w.extra["n_anchor"],
+                                                 w.extra["anchor_seed"])).to(dev)
+    anchors = ix.kmeanspp(w.extra["n_anchor"], u)
+    torch.cuda.synchronize()
+    rep["kmeanspp_s"] = round(time.perf_counter() - t0, 3)
+    log("anchors: %.2f s" % rep["kmeanspp_s"])
+    qt = w.train_queries(db)
+    d_qt = torch.from_numpy(qt).to(dev)
+    t0 = time.perf_counter()
+    labels = ix.seed_labels(anchors, d_qt)
+    torch.cuda.synchronize()
+    rep["labels_s"] = round(time.perf_counter() - t0, 3)
+    log("labels of %d training queries: %.2f s" % (len(qt), rep["labels_s"]))
+    params = torch.from_numpy(hn_inputs.mlp_init(w.extra["train_seed"] + 1)).to(dev)
+    t0 = time.perf_counter()
+    losses = hn.seed_train(params, d_qt, labels, batch=ARGS.batch, epochs=ARGS.epochs,
+                           lr=ARGS.lr)
+    torch.cuda.synchronize()
+    rep["train_s"] = round(time.perf_counter() - t0, 3)
+    ls = losses.cpu().numpy()
+    steps_per_epoch = max(1, len(ls) // max(1, ARGS.epochs))
+    rep.update({"train_queries": len(qt), "epochs": ARGS.epochs, "batch": ARGS.batch,
+                "lr": ARGS.lr, "loss_first_epoch": round(float(ls[:steps_per_epoch].mean()), 4),
+                "loss_last_epoch": round(float(ls[-steps_per_epoch:].mean()), 4),
+                "anchors": w.extra["n_anchor"]})
+    log("training: %.2f s, loss %.3f -> %.3f" % (rep["train_s"], rep["loss_first_epoch"],
+                                                 rep["loss_last_epoch"]))
+    ix.set_seed_model(params, anchors)
+    return rep
 
 
 def timed(fn, steps, warmup, torch):
@@ -100,7 +151,10 @@ def main():
     import paper_2606_27280_amd as hn
     from paper_2606_27280_amd import accounting as acc
 
+    global ARGS
+    ARGS = args
     w = hn_inputs.workload(args.workload)
+    seed = args.seed or ("learned" if args.workload == 5 else "plain")
     log("generating %s (N=%d, K=%d, alpha=%g)" % (w.name, w.n, w.k, w.alpha))
     db = w.db()
     qs = w.queries(db)
@@ -112,13 +166,17 @@ def main():
     ix = hn.Index(d_db, w.k, w.alpha)
     idx = torch.empty(Q, dtype=torch.int64, device=dev)
     sim = torch.empty(Q, dtype=torch.float64, device=dev)
+    seed_report = None
+    if args.workload == 5 or seed == "learned":
+        seed_report = build_seed_model(hn, ix, w, db, dev, torch)
     kw = dict(precision=args.precision, query_tiles=args.query_tiles,
-              chunk_blocks=args.chunk_blocks)
+              chunk_blocks=args.chunk_blocks, seed=seed)
 
     def step():
         ix.search(d_q, out=(idx, sim), **kw)
 
-    log("warmup %d + timed %d steps (%s)" % (args.warmup, args.steps, args.precision))
+    log("warmup %d + timed %d steps (%s, %s seed)" % (args.warmup, args.steps, args.precision,
+                                                     seed))
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -132,14 +190,19 @@ def main():
     kernels = {k: {"avg_ms": v["ms"] / v["launches"], "launches": v["launches"],
                    "total_ms": v["ms"]} for k, v in prof.result.items()}
     dom = max((k for k in kernels if k.startswith("scan_")), key=lambda k: kernels[k]["total_ms"])
+    # one step scans all Q queries once per scan kind, in one launch or (the
+    # single-pass forms) in query batches: the work per launch is the step's
+    # work divided by the launches per step
+    per_step = kernels[dom]["launches"] / args.steps
     avg_s = kernels[dom]["avg_ms"] / 1e3
-    flops = acc.scan_flops(Q, w.n, w.k)
+    flops = acc.scan_flops(Q, w.n, w.k) / per_step
     peak = PEAK[{"f32": "fp32_mfma_tflops", "bf16": "bf16_mfma_tflops",
                  "fp8": "fp8_mfma_tflops"}[dom.rsplit("_", 1)[1]]]
     achieved = flops / avg_s / 1e12
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                "algorithmic": "2*Q*N*K = %.4g flop per launch" % flops}
+                "algorithmic": "2*Q*N*K / %d launches per step = %.4g flop per launch" % (
+                    per_step, flops)}
 
     # exactness of this run against the GPU exhaustive search, pruned fraction
     _, _, aux = ix.search(d_q, aux=True, **kw)
@@ -176,10 +239,28 @@ def main():
             if prec == args.precision:
                 forms[prec] = round(qps, 1)
                 continue
-            s2, _ = timed(lambda: ix.search(d_q, out=(idx, sim), precision=prec),
+            s2, _ = timed(lambda: ix.search(d_q, out=(idx, sim), precision=prec, seed=seed),
                           args.steps, 2, torch)
             forms[prec] = round(Q * args.steps / s2, 1)
         log("forms: %s" % forms)
+    seed_forms = {}
+    if seed_report is not None:
+        # every seed form at the timed precision: queries/s, first-pass
+        # survivors per query, exactness against the timed form
+        for sf in ("plain", "learned", "window"):
+            log("seed form %s" % sf)
+            kws = dict(kw, seed=sf)
+            i2, s2_, a2 = ix.search(d_q, aux=True, **kws)
+            same = bool(torch.equal(i2, idx) and torch.equal(s2_, sim))
+            t2, _ = timed(lambda: ix.search(d_q, out=(i2, s2_), **kws), args.steps, 1, torch)
+            seed_forms[sf] = {"queries_per_s": round(Q * args.steps / t2, 1),
+                              "survivors_per_query": round(float(
+                                  a2["survivors"].double().mean()), 2),
+                              "mean_seed_sim": round(float(torch.nan_to_num(
+                                  a2["seed_sim"], neginf=float("nan")).nanmean()), 5)
+                              if sf != "window" else None,
+                              "same_result": same}
+        log("seed forms: %s" % seed_forms)
 
     res = {
         "metric": METRIC,
@@ -196,7 +277,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": 128, "k": w.k, "alpha": w.alpha,
                    "queries": Q, "query_mix": "%d perturbed + %d fresh" % (w.n_perturbed, w.n_fresh),
-                   "clusters": w.n_clusters, "precision": args.precision, "seed": "plain",
+                   "clusters": w.n_clusters, "precision": args.precision, "seed": seed,
                    "rescoring": "f64"},
         "pruned_pct": round(pruned_pct, 4),
         "survivors_per_query": round(float(surv.mean()), 2),
@@ -206,6 +287,9 @@ def main():
         "forms_queries_per_s": forms,
     }
     res.update(out)
+    if seed_report is not None:
+        res["seed_model"] = seed_report
+        res["seed_forms"] = seed_forms
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(db, qs, w.k, w.alpha, args.cpu_seconds)

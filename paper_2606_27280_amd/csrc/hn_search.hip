@@ -927,11 +927,57 @@ int64_t window_batch(int64_t n) {
     return std::max<int64_t>(256, ((int64_t)1 << 29) / window_per_query(n));
 }
 
-// One batch of queries through the whole pipeline.
+// Queries whose survivor pairs did not all fit the list, collected for a
+// second pass instead of the exhaustive fallback: the best candidate each one
+// reached (a real entry, so its sim is an admissible lower bound) becomes its
+// seed for a plain filter pass.
+struct Overflow {
+    int32_t *list = nullptr;      // [q] positions in the batch
+    double *lower = nullptr;      // [q] best sim reached
+    int64_t *lower_idx = nullptr; // [q] its entry (-1: none)
+    unsigned long long *count = nullptr;
+    int64_t n = 0;                // host copy of *count after the batch
+};
+
+__global__ __launch_bounds__(256) void collect_overflow(const int32_t *qflag, const QNorm *qn,
+                                                        const unsigned long long *best_key,
+                                                        const int32_t *best_idx, int64_t q,
+                                                        Overflow O) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= q || !qflag[i] || qn[i].bad) return;
+    const unsigned long long pos = atomicAdd(O.count, 1ull);
+    const unsigned long long k = best_key[i];
+    const bool any = k != 0ull && best_idx[i] != kIdxNone;
+    O.list[pos] = (int32_t)i;
+    O.lower[pos] = any ? sim_of_key(k) : -INFINITY;
+    O.lower_idx[pos] = any ? (int64_t)best_idx[i] : -1;
+}
+
+__global__ void gather_queries(const float *__restrict__ q, const int32_t *__restrict__ list,
+                               int64_t n, float *__restrict__ out) {
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n * kDim;
+         t += (int64_t)gridDim.x * 256)
+        out[t] = q[(int64_t)list[t / kDim] * kDim + t % kDim];
+}
+
+__global__ void scatter_results(const int32_t *__restrict__ list, int64_t n,
+                                const int64_t *__restrict__ idx, const double *__restrict__ sim,
+                                int64_t *__restrict__ out_idx, double *__restrict__ out_sim) {
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * 256) {
+        out_idx[list[j]] = idx[j];
+        out_sim[list[j]] = sim[j];
+    }
+}
+
+// One batch of queries through the whole pipeline.  lower_in: the plain
+// pipeline with given seeds (no argmax scan).  ov: collect the overflowing
+// queries instead of finishing them with the exhaustive fallback.
 int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *out_idx,
                  double *out_sim, const hn_search_opts &o, const hn_search_aux *aux,
-                 hn_search_stats *stats, hipStream_t s) {
-    const bool single = o.seed != HN_SEED_PLAIN;
+                 hn_search_stats *stats, hipStream_t s, const double *lower_in = nullptr,
+                 const int64_t *lower_idx_in = nullptr, Overflow *ov = nullptr) {
+    const bool single = o.seed != HN_SEED_PLAIN && !lower_in;
     const int64_t cap =
         o.survivor_cap > 0
             ? o.survivor_cap
@@ -939,7 +985,7 @@ int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *o
                                           (int64_t)1 << 29)
                       : default_cap(ix->n, q));
     Work W;
-    int rc = stage_seed(ix, queries, q, o, nullptr, nullptr, cap, W, s, single);
+    int rc = stage_seed(ix, queries, q, o, lower_in, lower_idx_in, cap, W, s, single);
     if (rc) return rc;
     ScanArgs A = filter_args(ix, W, q, W.pairs, cap);
     if (single) {
@@ -1013,7 +1059,11 @@ int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *o
     F.best_key = W.best_key;
     F.best_idx = W.best_idx;
     F.cnt = W.cnt;
-    {
+    if (ov) {
+        hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, s, ov->count, 1);
+        hipLaunchKernelGGL(collect_overflow, dim3(blocks_for(q)), dim3(256), 0, s, W.qflag, W.qn,
+                           W.best_key, W.best_idx, q, *ov);
+    } else {
         ProfScope prof_(s, "fallback");
         hipLaunchKernelGGL(fallback_kernel, dim3((unsigned)std::min<int64_t>(q, 1024)), dim3(256), 0,
                            s, F);
@@ -1048,6 +1098,45 @@ int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *o
         stats->survivors = (int64_t)h[0];
         stats->overflow_queries = (int64_t)h[1];
     }
+    if (ov) {
+        unsigned long long h = 0;
+        HN_HIP(hipMemcpyAsync(&h, ov->count, sizeof h, hipMemcpyDeviceToHost, s));
+        HN_HIP(hipStreamSynchronize(s));
+        ov->n = (int64_t)h;
+    }
+    return HN_OK;
+}
+
+// A single-pass batch, then its overflowing queries again as a plain filter
+// pass seeded with the best candidate each reached (exact: every entry that
+// can beat that candidate survives the filter; the candidate is the seed).
+int single_pass_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *out_idx,
+                      double *out_sim, const hn_search_opts &o, const hn_search_aux *aux,
+                      hn_search_stats *stats, hipStream_t s) {
+    Arena *ar = nullptr;
+    int rc = arena_for((void *)s, (size_t)q * (4 + 8 + 8 + 8 + 8 + kDim * 4) + 8 * 256, &ar, 2);
+    if (rc) return rc;
+    Overflow ov;
+    ov.list = ar->take<int32_t>(q);
+    ov.lower = ar->take<double>(q);
+    ov.lower_idx = ar->take<int64_t>(q);
+    ov.count = ar->take<unsigned long long>(1);
+    int64_t *sub_idx = ar->take<int64_t>(q);
+    double *sub_sim = ar->take<double>(q);
+    float *sub_q = ar->take<float>(q * kDim);
+    rc = search_batch(ix, queries, q, out_idx, out_sim, o, aux, stats, s, nullptr, nullptr, &ov);
+    if (rc || ov.n == 0) return rc;
+    hipLaunchKernelGGL(gather_queries, dim3(blocks_for(ov.n * kDim)), dim3(256), 0, s, queries,
+                       ov.list, ov.n, sub_q);
+    hn_search_opts o2 = o;
+    o2.seed = HN_SEED_PLAIN;
+    o2.survivor_cap = 0;
+    rc = search_batch(ix, sub_q, ov.n, sub_idx, sub_sim, o2, nullptr, nullptr, s, ov.lower,
+                      ov.lower_idx, nullptr);
+    if (rc) return rc;
+    hipLaunchKernelGGL(scatter_results, dim3(blocks_for(ov.n)), dim3(256), 0, s, ov.list, ov.n,
+                       sub_idx, sub_sim, out_idx, out_sim);
+    HN_HIP(hipGetLastError());
     return HN_OK;
 }
 
@@ -1083,8 +1172,12 @@ extern "C" int hn_search_top1(const hn_index *ix, const float *queries, int64_t 
             a2.slack = aux->slack ? aux->slack + q0 : nullptr;
         }
         hn_search_stats st{0, 0};
-        rc = search_batch(ix, queries + q0 * kDim, nb, out_idx + q0, out_sim + q0, o,
-                          aux ? &a2 : nullptr, stats ? &st : nullptr, s);
+        if (o.seed == HN_SEED_PLAIN)
+            rc = search_batch(ix, queries + q0 * kDim, nb, out_idx + q0, out_sim + q0, o,
+                              aux ? &a2 : nullptr, stats ? &st : nullptr, s);
+        else
+            rc = single_pass_batch(ix, queries + q0 * kDim, nb, out_idx + q0, out_sim + q0, o,
+                                   aux ? &a2 : nullptr, stats ? &st : nullptr, s);
         if (rc) return rc;
         if (stats) {
             stats->survivors += st.survivors;

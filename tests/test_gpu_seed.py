@@ -310,3 +310,21 @@ def test_trained_seed_gains_over_untrained(hn):
     assert L_t > L_u
     assert s_t < s_u
     ix.close()
+
+
+def test_single_pass_overflow_rerun_exact(hn):
+    """A pair list far too small for the window: the overflowing queries are
+    finished by a filter pass seeded with the best candidate they reached."""
+    w = hn_inputs.workload(1)
+    db = w.db()
+    qs = w.queries(db)
+    ix = hn.Index(dev(db), w.k, w.alpha)
+    ref = oracle.bnb_top1(db, qs, w.k, w.alpha)
+    for prec in ("fp32", "bf16"):
+        say("window form with survivor_cap=3000, precision=%s" % prec)
+        idx, sim, st = ix.search(dev(qs), precision=prec, seed="window", survivor_cap=3000,
+                                 stats=True)
+        assert st["overflow_queries"] > 0
+        assert (idx.cpu().numpy() == ref["idx"]).all()
+        assert (np.abs(sim.cpu().numpy() - ref["sim"]) <= SIM_TOL).all()
+    ix.close()
