@@ -278,6 +278,38 @@ int hn_seed_labels(const hn_index *ix, const int64_t *anchors, int32_t n_anchor,
 int hn_set_seed_model(hn_index *ix, const float *params, const int64_t *anchors,
                       int32_t n_anchor, void *stream);
 
+/* ---------------------------------------------------------- many databases
+ * Ragged query batches against many indexes in one search: every scan is a
+ * single persistent launch over the work items of all databases of one stream
+ * width (bf16 and fp8: one launch for all k <= 16), the per-query kernels look
+ * up their database, and results are exactly those of hn_search_top1 on each
+ * index.  A plan owns all buffers and tables: hn_multi_search allocates
+ * nothing and never synchronises, and with use_graph it replays a HIP graph
+ * captured on the first call (captured again when a pointer changes). */
+typedef struct hn_multi_plan hn_multi_plan; /* opaque */
+
+/* Plan a search of q_counts[d] queries (host int64 [n_db], >= 0) against
+ * ixs[d] (each k <= 32, all on the current device) with the given options
+ * (precision, query_tiles, chunk_blocks, survivor_cap, beta; the seed must be
+ * HN_SEED_PLAIN, else HN_ERR_UNSUPPORTED).  Synchronises.  The indexes must
+ * outlive the plan. */
+int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db, const int64_t *q_counts,
+                         const hn_search_opts *opts, hn_multi_plan **out);
+
+/* Run a plan: queries device float32 [sum q_counts][128] (16-byte aligned),
+ * database by database in order; out_idx int64 and out_sim double [sum
+ * q_counts] in the same order (indices into each query's own database).
+ * use_graph != 0: launch the plan's captured graph on `stream`. */
+int hn_multi_search(hn_multi_plan *plan, const float *queries, int64_t *out_idx,
+                    double *out_sim, int32_t use_graph, void *stream);
+
+/* Plan facts (host outputs, any may be NULL): total queries, scan work items
+ * (per scan pass), scan launches per search. */
+int hn_multi_plan_info(const hn_multi_plan *plan, int64_t *total_queries, int64_t *work_items,
+                       int32_t *scan_launches);
+
+void hn_multi_plan_free(hn_multi_plan *plan);
+
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *hn_last_error(void);
 

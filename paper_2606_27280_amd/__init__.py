@@ -17,7 +17,7 @@ from ._lib import (HN_BUILD_LOW_PRECISION, HN_BUILD_NO_VALIDATE, HN_MLP_PARAMS, 
 __all__ = ["Index", "bruteforce_top1", "profile", "HNError", "PRECISIONS", "SEEDS",
            "HN_PREC_FP32", "HN_PREC_BF16", "HN_PREC_FP8", "HN_SEED_PLAIN", "HN_SEED_LEARNED",
            "HN_SEED_WINDOW", "HN_BUILD_NO_VALIDATE", "HN_BUILD_LOW_PRECISION", "HN_MLP_PARAMS",
-           "mlp_forward", "mlp_grad", "mlp_adamw", "seed_train"]
+           "mlp_forward", "mlp_grad", "mlp_adamw", "seed_train", "MultiPlan"]
 
 PRECISIONS = {"fp32": HN_PREC_FP32, "bf16": HN_PREC_BF16, "fp8": HN_PREC_FP8}
 SEEDS = {"plain": HN_SEED_PLAIN, "learned": HN_SEED_LEARNED, "window": HN_SEED_WINDOW}
@@ -190,6 +190,59 @@ class Index:
         ap = _dev(anchors, torch.int64, "anchors", 1)
         _lib.check(_lib.lib().hn_set_seed_model(self._h, pp, ap, anchors.shape[0],
                                                 _stream(stream)))
+
+
+class MultiPlan:
+    """hn_multi_plan_create / hn_multi_search: one search of ragged query
+    batches against several indexes (the plain two-pass seed)."""
+
+    def __init__(self, indexes, q_counts, precision="fp32", query_tiles=0, chunk_blocks=0,
+                 survivor_cap=0, beta=None):
+        n = len(indexes)
+        if n != len(q_counts):
+            raise ValueError("one query count per index")
+        self._indexes = list(indexes)  # keep them alive
+        hs = (ctypes.c_void_p * n)(*[ix._h.value for ix in indexes])
+        qc = (ctypes.c_int64 * n)(*[int(c) for c in q_counts])
+        o = _opts(precision, query_tiles, chunk_blocks, survivor_cap, beta)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().hn_multi_plan_create(hs, n, qc, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.q_counts = [int(c) for c in q_counts]
+        self.total = sum(self.q_counts)
+
+    def info(self):
+        tq, wi, sl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _lib.check(_lib.lib().hn_multi_plan_info(self._h, ctypes.byref(tq), ctypes.byref(wi),
+                                                 ctypes.byref(sl)))
+        return {"total_queries": tq.value, "work_items": wi.value, "scan_launches": sl.value}
+
+    def search(self, queries, use_graph=True, out=None, stream=None):
+        """(idx int64 [total], sim float64 [total]) for the concatenated
+        queries (database by database)."""
+        torch = _torch()
+        qp = _dev(queries, torch.float32, "queries", 2)
+        if queries.shape[0] != self.total:
+            raise ValueError("queries must hold %d rows" % self.total)
+        if out is None:
+            idx = torch.empty(self.total, dtype=torch.int64, device=queries.device)
+            sim = torch.empty(self.total, dtype=torch.float64, device=queries.device)
+        else:
+            idx, sim = out
+        _lib.check(_lib.lib().hn_multi_search(self._h, qp, _ptr(idx), _ptr(sim),
+                                              1 if use_graph else 0, _stream(stream)))
+        return idx, sim
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().hn_multi_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _adamw(lr, beta1, beta2, eps, weight_decay):

@@ -79,6 +79,12 @@ SIGNATURES = {
     "hn_kmeanspp": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "hn_seed_labels": (_i32, [_vp, _vp, _i32, _vp, _i64, _vp, _vp]),
     "hn_set_seed_model": (_i32, [_vp, _vp, _vp, _i32, _vp]),
+    "hn_multi_plan_create": (_i32, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_i64),
+                                    ctypes.POINTER(SearchOpts), ctypes.POINTER(_vp)]),
+    "hn_multi_search": (_i32, [_vp, _vp, _vp, _vp, _i32, _vp]),
+    "hn_multi_plan_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                  ctypes.POINTER(_i32)]),
+    "hn_multi_plan_free": (None, [_vp]),
     "hn_last_error": (ctypes.c_char_p, []),
 }
 

@@ -1,0 +1,709 @@
+// Device side of the search pipeline, shared by the single-database search
+// (hn_search.hip) and the multi-database search (hn_multi.hip): query
+// preparation, seed selection with the bound slack, float64 rescoring, the
+// deterministic argmax, the exact overflow fallback, the output writer and
+// the exhaustive baseline's helpers.  Internal to the library.
+#pragma once
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "hn_scan.h"
+
+namespace hn {
+namespace {
+
+constexpr double kU32 = 1.0 / 8388608.0;               // 2^-23 (covers RNE and truncation)
+constexpr double kU64 = 1.0 / 9007199254740992.0;      // 2^-53
+constexpr double kUbf16 = 1.0 / 256.0;                 // 2^-8, bf16 round-to-nearest
+constexpr int kIdxNone = 0x7fffffff;
+// Scan bookkeeping words zeroed by prep_queries: [0,8) item counters of the
+// first scan, [8,16) of the second, 16 and 17 their redo counts.
+constexpr int kWorkWords = 32;
+
+// ---------------------------------------------------------------- queries
+
+struct QNorm {
+    double major, minor, full;  // rounded-up float64 block norms
+    double res16;               // ||bf16(q[:k]) - q[:k]||, rounded up
+    double res8;                // ||s8 fp8(q[:k] / s8) - q[:k]||, rounded up
+    float sc8;                  // s8: power-of-two scale of the fp8 operand
+    int bad;                    // non-finite component
+};
+
+__device__ __forceinline__ float bf16_rne(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xffff0000u);
+}
+
+// Query operands for the scans (any pointer may be NULL), widths per stream.
+struct PrepArgs {
+    const float *q;
+    int64_t nq, q_pad;
+    int k;
+    int w32, w16, w8;
+    float *op32;
+    uint16_t *op16;
+    uint8_t *op8;
+    QNorm *qn;
+    unsigned *work;
+};
+
+// Query i (of the padded batch): norms and the float32 / bf16 / fp8 operands.
+__device__ __forceinline__ void prep_one(const PrepArgs &P, const int64_t i) {
+    if (i >= P.q_pad) return;
+    if (i >= P.nq) {
+        if (P.op32)
+            for (int c = 0; c < P.w32; ++c) P.op32[i * P.w32 + c] = 0.0f;
+        if (P.op16)
+            for (int c = 0; c < P.w16; ++c) P.op16[i * P.w16 + c] = 0;
+        if (P.op8)
+            for (int c = 0; c < P.w8; ++c) P.op8[i * P.w8 + c] = 0;
+        return;
+    }
+    const int k = P.k;
+    const float *v = P.q + i * kDim;
+    double sM = 0, sm = 0, sr = 0;
+    float amax = 0.0f;
+    bool finite = true;
+    for (int j = 0; j < kDim; ++j) {
+        float f = v[j];
+        finite = finite && isfinite(f);
+        double d = (double)f;
+        if (j < k) {
+            sM = fma(d, d, sM);
+            double b = (double)bf16_rne(f);
+            sr = fma(b - d, b - d, sr);
+            amax = fmaxf(amax, fabsf(f));
+        } else {
+            sm = fma(d, d, sm);
+        }
+    }
+    const double up = 1.0 + ldexp(1.0, -40);
+    QNorm r;
+    r.major = sqrt(sM) * up;
+    r.minor = sqrt(sm) * up;
+    r.full = sqrt(sM + sm) * up;
+    r.res16 = sqrt(sr) * up;
+    r.res8 = 0.0;
+    r.sc8 = 1.0f;
+    r.bad = finite ? 0 : 1;
+    if (P.op32)
+        for (int c = 0; c < P.w32; ++c) P.op32[i * P.w32 + c] = (c < k && finite) ? v[c] : 0.0f;
+    if (P.op16)
+        for (int c = 0; c < P.w16; ++c)
+            P.op16[i * P.w16 + c] =
+                (c < k && finite) ? (uint16_t)(__float_as_uint(bf16_rne(v[c])) >> 16) : 0;
+    if (P.op8) {
+        const float sc = finite ? fp8_scale_for(amax) : 1.0f;
+        const float inv = 1.0f / sc;  // exact: a power of two
+        double s8 = 0;
+        for (int c = 0; c < P.w8; ++c) {
+            const float f = (c < k && finite) ? v[c] : 0.0f;
+            const uint8_t code = fp8_e4m3(f * inv);
+            P.op8[i * P.w8 + c] = code;
+            const double e = (double)fp8_e4m3_value(code) * (double)sc - (double)f;
+            s8 = fma(e, e, s8);
+        }
+        r.res8 = sqrt(s8) * up;
+        r.sc8 = sc;
+    }
+    P.qn[i] = r;
+}
+
+// One thread per (padded) query; also zeroes the scan bookkeeping words.
+__global__ __launch_bounds__(256) void prep_queries(PrepArgs P) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (P.work && i < kWorkWords) P.work[i] = 0u;
+    prep_one(P, i);
+}
+
+// ---------------------------------------------------------------- seed
+
+struct SeedArgs {
+    const float *part_val;
+    const int32_t *part_idx;
+    int32_t n_chunks, q_pad;
+    int32_t shape, group_size;  // scan tile shape (16 or 32) and entries per lane group
+    const float *queries;
+    int64_t q;
+    const float *rows;
+    int64_t n;
+    int32_t k;
+    double alpha, beta;  // beta = alpha for exact search
+    double mu_major, mu_minor, mu_full;
+    // scan slack: worst case rel * major * mu, or the residual-norm form
+    // res_q * res_mu + major * res_x + acc_rel * (major + res_q) * res_mu,
+    // or the smaller of the two; plus abs
+    double scan_rel, scan_mu, scan_abs;
+    int scan_res;  // 0: worst case; 1: min(worst case, residual); 2: residual
+    int fp8;       // residuals of the fp8 operands; thresholds in scan units
+    double res_mu, res_x, res_acc_rel;
+    double scale_x;  // fp8: power-of-two scale of the entry copy
+    const double *lower;  // given L (filter-only, learned or no seed); NULL: plain seed
+    const int64_t *lower_idx;  // entry of each given L, or NULL (none)
+    // single-pass window (NULL: none): exact width 2 (beta + eps_q) in scan
+    // units, the float width the scan subtracts (widened for its rounding),
+    // and the scan's starting running maximum T_q + width
+    double *win;
+    float *win_scan, *init_best;
+    double bound_mu;  // max norm of the scanned entry copy (bounds |s~|)
+    const QNorm *qn;
+    float *thr;           // [q_pad]: scan threshold T_q (+inf for padding)
+    float *thr32;         // [q]: float32 re-check threshold, or NULL
+    int64_t *seed_idx;
+    double *seed_sim;
+    double *slack;
+    unsigned long long *best_key;
+    int32_t *best_idx;
+    int32_t *cnt;
+    int32_t *qflag;
+    unsigned long long *counter;
+};
+
+__device__ __forceinline__ float round_down_f32(double v) { return __double2float_rd(v); }
+
+// Entry of slot v of an argmax lane group gid = block * G + g, for the scan's
+// tile shape: 16x16 tiles give 4 consecutive entries, 32x32 tiles 16 entries
+// (rows 8 (v / 4) + 4 g + v % 4 of the block).
+__device__ __forceinline__ int64_t group_entry(int shape, int gid, int v) {
+    if (shape == 16) return (int64_t)(gid >> 2) * 16 + 4 * (gid & 3) + v;
+    return (int64_t)(gid >> 1) * 32 + 8 * (v >> 2) + 4 * (gid & 1) + (v & 3);
+}
+
+// Query i, one wave: reduce the per-chunk argmax partials, rescore every
+// entry of the winning lane group in float64 (one lane each) and keep the
+// best (sim desc, index asc) as the seed; then the slack and thresholds.
+__device__ __forceinline__ void seed_one(const SeedArgs &S, const int64_t i, const int lane) {
+    if (i >= S.q_pad) return;
+    if (i >= S.q) {
+        if (lane == 0) {
+            S.thr[i] = INFINITY;
+            if (S.win_scan) {
+                S.win_scan[i] = 0.0f;
+                S.init_best[i] = -INFINITY;
+            }
+        }
+        return;
+    }
+    const QNorm qn = S.qn[i];
+    if (qn.bad) {
+        if (lane == 0) {
+            S.best_idx[i] = kIdxNone;
+            S.cnt[i] = 0;
+            S.qflag[i] = 0;
+            S.thr[i] = INFINITY;
+            if (S.thr32) S.thr32[i] = INFINITY;
+            S.seed_idx[i] = -1;
+            S.seed_sim[i] = NAN;
+            S.slack[i] = NAN;
+            S.best_key[i] = 0;
+            if (S.win_scan) {
+                S.win[i] = 0.0;
+                S.win_scan[i] = 0.0f;
+                S.init_best[i] = INFINITY;
+            }
+        }
+        return;
+    }
+    const float *qv = S.queries + i * kDim;
+    double L;
+    int64_t b = -1;
+    if (S.lower) {
+        L = S.lower[i];
+        b = S.lower_idx ? S.lower_idx[i] : -1;
+    } else {
+        float bv = -INFINITY;
+        int bi = -1;
+        for (int c = lane; c < S.n_chunks; c += 64)
+            lex_merge(bv, bi, S.part_val[(int64_t)c * S.q_pad + i],
+                      S.part_idx[(int64_t)c * S.q_pad + i]);
+        for (int o = 32; o > 0; o >>= 1) {
+            const float ov = __shfl_xor(bv, o);
+            const int oi = __shfl_xor(bi, o);
+            lex_merge(bv, bi, ov, oi);
+        }
+        double sv = -INFINITY;
+        int64_t e = -1;
+        if (bi >= 0 && lane < S.group_size) {
+            e = group_entry(S.shape, bi, lane);
+            if (e < S.n)
+                sv = sim64(qv, S.rows + e * kDim);
+            else
+                e = -1;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double os = __shfl_xor(sv, o);
+            const int64_t oe = __shfl_xor(e, o);
+            if (oe >= 0 && (e < 0 || os > sv || (os == sv && oe < e))) {
+                sv = os;
+                e = oe;
+            }
+        }
+        L = sv;
+        b = e;
+    }
+    if (lane != 0) return;
+    S.best_idx[i] = kIdxNone;
+    S.cnt[i] = 0;
+    S.qflag[i] = 0;
+    // slack: scan rounding + stored-norm excess (Eq. 3) + float64 evaluation
+    double es = S.scan_rel * qn.major * S.scan_mu;
+    if (S.scan_res) {
+        const double rq = S.fp8 ? qn.res8 : qn.res16;
+        const double er =
+            rq * S.res_mu + qn.major * S.res_x + S.res_acc_rel * (qn.major + rq) * S.res_mu;
+        es = S.scan_res == 2 ? er : fmin(es, er);
+    }
+    es += S.scan_abs;
+    double en = fmax(0.0, qn.minor * S.mu_minor - S.alpha);
+    double e64 = gamma_n(kDim, kU64) * qn.full * S.mu_full;
+    double eps = (es + en + e64) * (1.0 + ldexp(1.0, -30)) + ldexp(1.0, -40);
+    // fp8 scans score q~ . x~ with q = s_q q~ and x = s_x x~ (powers of two):
+    // the threshold in scan units is the same bound divided by s_q s_x, exact
+    const double unit = S.fp8 ? 1.0 / ((double)qn.sc8 * S.scale_x) : 1.0;
+    S.thr[i] = round_down_f32((L - S.beta - eps) * unit);
+    if (S.win_scan) {
+        // |s~| <= (||q_M|| + r_q) max ||x^_M|| (1 + 2^-20), in scan units
+        const double rq = S.fp8 ? qn.res8 : (S.scan_res ? qn.res16 : 0.0);
+        const double bound = (qn.major + rq) * S.bound_mu * unit * (1.0 + ldexp(1.0, -20));
+        const double w = 2.0 * (S.beta + eps) * unit;
+        S.win[i] = w;
+        S.win_scan[i] = __double2float_ru(w + ldexp(1.0, -21) * (bound + w));
+        S.init_best[i] = round_down_f32((L - S.beta - eps) * unit + w);
+    }
+    if (S.thr32) {
+        double e32 = gamma_n(S.k, kU32) * qn.major * S.mu_major + S.k * ldexp(1.0, -125);
+        double eps32 = (e32 + en + e64) * (1.0 + ldexp(1.0, -30)) + ldexp(1.0, -40);
+        S.thr32[i] = round_down_f32(L - S.beta - eps32);
+    }
+    S.seed_idx[i] = b;
+    S.seed_sim[i] = L;
+    S.slack[i] = eps;
+    S.best_key[i] = b >= 0 ? key_of(L) : 0ull;
+}
+
+// One wave per query; also zeroes the survivor-list counter.
+__global__ __launch_bounds__(256) void seed_kernel(SeedArgs S) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i == 0 && lane == 0) *S.counter = 0;
+    seed_one(S, i, lane);
+}
+
+// The scan stream and query operands of a precision.
+int stream_width(const hn_index *ix, int precision) {
+    return precision == HN_PREC_FP32 ? ix->kp : (precision == HN_PREC_BF16 ? ix->kb : ix->k8);
+}
+const void *stream_of(const hn_index *ix, int precision) {
+    return precision == HN_PREC_FP32   ? (const void *)ix->major32
+           : precision == HN_PREC_BF16 ? (const void *)ix->major16
+                                       : (const void *)ix->major8;
+}
+int check_precision(const hn_index *ix, int precision) {
+    if (precision != HN_PREC_FP32 && precision != HN_PREC_BF16 && precision != HN_PREC_FP8)
+        return fail(HN_ERR_UNSUPPORTED, "precision %d is not available", precision);
+    if (precision == HN_PREC_FP8 && ix->k8 == 0)
+        return fail(HN_ERR_UNSUPPORTED, "the fp8 scan needs k <= 32 (k = %d)", ix->k);
+    return HN_OK;
+}
+
+// Survivor-list capacity of the two-pass search: max(2048, n / 512) pairs
+// per query, at least 2^20 and at most 2^28.
+int64_t default_cap(int64_t n, int64_t q) {
+    int64_t per = std::max<int64_t>(2048, n / 512);
+    int64_t c = q * per;
+    return std::min<int64_t>(std::max<int64_t>(c, (int64_t)1 << 20), (int64_t)1 << 28);
+}
+
+// The scan-rounding part of the slack for a precision (Section 3.3's bound
+// made admissible for the low-precision scans).
+inline void scan_slack(const hn_index *ix, int precision, SeedArgs &S) {
+    if (precision == HN_PREC_FP32) {
+        S.scan_rel = gamma_n(ix->k, kU32);
+        S.scan_mu = ix->mu_major;
+        S.scan_abs = ix->k * ldexp(1.0, -125);
+        S.scan_res = 0;
+    } else if (precision == HN_PREC_BF16) {
+        // worst case: both roundings relative 2^-8, then float32 accumulation
+        const double ub = kUbf16;
+        S.scan_rel = (2 * ub + ub * ub) + gamma_n(ix->k, kU32) * (1 + ub) * (1 + ub);
+        S.scan_mu = ix->mu_major;
+        S.scan_abs = ix->k * ldexp(1.0, -125);
+        // residual form (Cauchy-Schwarz on the rounding residuals):
+        // |sum(q^x^ - qx)| <= ||q^-q|| ||x^|| + ||q|| ||x^-x||, plus accumulation
+        S.scan_res = 1;
+        S.res_mu = ix->mu_major16;
+        S.res_x = ix->res16;
+        S.res_acc_rel = gamma_n(ix->k, kU32);
+    } else {
+        // fp8: the residual form only (subnormal codes have no relative
+        // bound); the products are summed by the bf16 matrix core (the codes
+        // are decoded exactly to bf16), float32 accumulation.
+        S.scan_rel = 0.0;
+        S.scan_mu = 0.0;
+        S.scan_abs = ix->k * ldexp(1.0, -125);
+        S.scan_res = 2;
+        S.fp8 = 1;
+        S.scale_x = ix->scale8;
+        S.res_mu = ix->mu_major8;
+        S.res_x = ix->res8;
+        S.res_acc_rel = gamma_n(ix->k, kU32);
+    }
+}
+
+// ------------------------------------------------------ rescoring & argmax
+
+// Per-database constants of a multi-database search, looked up by the
+// database of each (padded) query position.
+struct DbRef {
+    const float *rows;      // [n][128]
+    const float *major32;   // [n_pad][kp]
+    int64_t n;
+    int32_t kp, k;
+    double alpha, beta, mu_major, mu_minor, mu_full;
+    int64_t pad_base;       // first padded query position of the database
+    int64_t q;              // its real queries
+    int64_t out_base;       // their first position in the caller's outputs
+};
+
+struct RescoreArgs {
+    const int2 *pairs;
+    const float *pair_val;     // window mode: scan score of the pair
+    const unsigned long long *counter;
+    int64_t cap;
+    const float *queries, *rows;
+    const float *major32;      // re-check stream (low-precision scans)
+    int32_t kp, k;
+    const float *thr32;        // re-check / window threshold per query
+    double *psim;              // [cap]
+    unsigned long long *best_key;
+    int32_t *best_idx;
+    int32_t *cnt;
+    const int64_t *seed_idx;
+    const double *seed_sim;
+    int64_t q;
+    int count;  // count survivors per query (only when requested)
+    const DbRef *db;     // multi-database: per-database rows, stream, k
+    const int32_t *gdb;  //   and the database of each query position (or NULL)
+};
+
+__device__ __forceinline__ int64_t pair_count(const RescoreArgs &R) {
+    unsigned long long c = *R.counter;
+    return (int64_t)c < R.cap ? (int64_t)c : R.cap;
+}
+
+// MODE 0: plain; 1: float32 re-check against thr32 first; 2: window re-filter.
+template <int MODE>
+__global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs R) {
+    const int64_t m = pair_count(R);
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < m;
+         p += (int64_t)gridDim.x * 256) {
+        const int2 pr = R.pairs[p];
+        const float *qv = R.queries + (int64_t)pr.x * kDim;
+        const float *rows = R.rows, *major32 = R.major32;
+        int kp = R.kp, k = R.k;
+        if (R.gdb) {
+            const DbRef &D = R.db[R.gdb[pr.x]];
+            rows = D.rows;
+            major32 = D.major32;
+            kp = D.kp;
+            k = D.k;
+        }
+        if (R.count) atomicAdd(&R.cnt[pr.x], 1);
+        bool keep = true;
+        if (MODE == 1) {
+            const float *xm = major32 + (int64_t)pr.y * kp;
+            float s = 0.0f;
+            for (int j = 0; j < k; ++j) s = fmaf(qv[j], xm[j], s);
+            keep = s >= R.thr32[pr.x];
+        } else if (MODE == 2) {
+            keep = R.pair_val[p] >= R.thr32[pr.x];
+        }
+        double s = -INFINITY;
+        if (keep) {
+            s = sim64(qv, rows + (int64_t)pr.y * kDim);
+            atomicMax(&R.best_key[pr.x], key_of(s));
+        }
+        R.psim[p] = s;
+    }
+}
+
+__global__ __launch_bounds__(256) void tie_kernel(RescoreArgs R) {
+    const int64_t m = pair_count(R);
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < m + R.q;
+         p += (int64_t)gridDim.x * 256) {
+        if (p < m) {
+            const double s = R.psim[p];
+            if (s == -INFINITY) continue;
+            const int2 pr = R.pairs[p];
+            if (key_of(s) == R.best_key[pr.x]) atomicMin(&R.best_idx[pr.x], pr.y);
+        } else if (R.seed_idx) {
+            const int64_t qi = p - m;
+            const int64_t b = R.seed_idx[qi];
+            if (b >= 0 && key_of(R.seed_sim[qi]) == R.best_key[qi])
+                atomicMin(&R.best_idx[qi], (int32_t)b);
+        }
+    }
+}
+
+// Exact completion of queries whose survivors did not fit the pair list: one
+// work-group per flagged query scans every entry.  full = 1 evaluates every
+// entry (exhaustive baseline); otherwise the float64 major score with the
+// rigorous float64 slack decides which entries get the full sim.
+struct FallbackArgs {
+    const int32_t *qflag;
+    const QNorm *qn;
+    const float *queries, *rows;
+    int64_t q, n;
+    int32_t k, full;
+    double beta, alpha, mu_major, mu_minor, mu_full;
+    const double *seed_sim;
+    unsigned long long *best_key;
+    int32_t *best_idx;
+    int32_t *cnt;
+    const DbRef *db;     // multi-database (or NULL): per-database constants
+    const int32_t *gdb;
+};
+
+__global__ __launch_bounds__(256) void fallback_kernel(FallbackArgs F) {
+    __shared__ unsigned long long sk[256];
+    __shared__ int si[256];
+    __shared__ int sc[256];
+    for (int64_t qi = blockIdx.x; qi < F.q; qi += gridDim.x) {
+        // uniform: the reduction below holds barriers
+        if (!__builtin_amdgcn_readfirstlane(F.qflag[qi])) continue;
+        const float *qv = F.queries + qi * kDim;
+        const QNorm qn = F.qn[qi];
+        const float *rows = F.rows;
+        int64_t n = F.n;
+        int k = F.k;
+        double alpha = F.alpha, beta = F.beta, mu_major = F.mu_major, mu_minor = F.mu_minor,
+               mu_full = F.mu_full;
+        if (F.gdb) {
+            const DbRef &D = F.db[__builtin_amdgcn_readfirstlane(F.gdb[qi])];
+            rows = D.rows;
+            n = D.n;
+            k = D.k;
+            alpha = D.alpha;
+            beta = D.beta;
+            mu_major = D.mu_major;
+            mu_minor = D.mu_minor;
+            mu_full = D.mu_full;
+        }
+        double lim = -INFINITY;
+        if (!F.full) {
+            double en = fmax(0.0, qn.minor * mu_minor - alpha);
+            double e = gamma_n(k, kU64) * qn.major * mu_major + en +
+                       gamma_n(kDim, kU64) * qn.full * mu_full;
+            lim = F.seed_sim[qi] - beta - e * (1.0 + ldexp(1.0, -30)) - ldexp(1.0, -40);
+        }
+        unsigned long long bk = 0;
+        int bi = kIdxNone, c = 0;
+        for (int64_t e = threadIdx.x; e < n; e += 256) {
+            const float *xv = rows + e * kDim;
+            if (!F.full) {
+                double s = 0.0;
+                for (int j = 0; j < k; ++j) s = fma((double)qv[j], (double)xv[j], s);
+                if (s < lim) continue;
+            }
+            ++c;
+            unsigned long long kk = key_of(sim64(qv, xv));
+            if (kk > bk || (kk == bk && (int)e < bi)) {
+                bk = kk;
+                bi = (int)e;
+            }
+        }
+        sk[threadIdx.x] = bk;
+        si[threadIdx.x] = bi;
+        sc[threadIdx.x] = c;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) {
+                unsigned long long ok = sk[threadIdx.x + o];
+                int oi = si[threadIdx.x + o];
+                if (ok > sk[threadIdx.x] || (ok == sk[threadIdx.x] && oi < si[threadIdx.x])) {
+                    sk[threadIdx.x] = ok;
+                    si[threadIdx.x] = oi;
+                }
+                sc[threadIdx.x] += sc[threadIdx.x + o];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            F.best_key[qi] = sk[0];
+            F.best_idx[qi] = si[0];
+            F.cnt[qi] = sc[0];
+        }
+        __syncthreads();
+    }
+}
+
+struct FinalArgs {
+    int64_t q;
+    const QNorm *qn;
+    const unsigned long long *best_key;
+    const int32_t *best_idx;
+    const int32_t *cnt;
+    const int32_t *qflag;
+    int64_t *out_idx;
+    double *out_sim;
+    hn_search_aux aux;
+    const int64_t *seed_idx;
+    const double *seed_sim;
+    const float *thr;
+    const double *slack;
+    unsigned long long *n_flagged;
+    const DbRef *db;     // multi-database (or NULL): F.q counts padded
+    const int32_t *gdb;  //   positions; outputs go to out_base + local
+};
+
+__global__ __launch_bounds__(256) void finalize_kernel(FinalArgs F) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= F.q) return;
+    int64_t o = i;
+    if (F.gdb) {
+        const DbRef &D = F.db[F.gdb[i]];
+        const int64_t local = i - D.pad_base;
+        if (local >= D.q) return;
+        o = D.out_base + local;
+    }
+    const bool bad = F.qn[i].bad != 0;
+    F.out_idx[o] = bad ? -1 : (int64_t)F.best_idx[i];
+    F.out_sim[o] = bad ? (double)NAN : sim_of_key(F.best_key[i]);
+    if (F.aux.survivors) F.aux.survivors[o] = F.cnt[i];
+    if (F.aux.seed_idx) F.aux.seed_idx[o] = F.seed_idx ? F.seed_idx[i] : -1;
+    if (F.aux.seed_sim) F.aux.seed_sim[o] = F.seed_sim ? F.seed_sim[i] : (double)NAN;
+    if (F.aux.threshold) F.aux.threshold[o] = F.thr ? F.thr[i] : (float)NAN;
+    if (F.aux.slack) F.aux.slack[o] = F.slack ? F.slack[i] : (double)NAN;
+    if (F.n_flagged && F.qflag[i]) atomicAdd(F.n_flagged, 1ull);
+}
+
+// ------------------------------------------------- brute-force helpers
+
+__global__ __launch_bounds__(256) void bf_db_norm(const float *__restrict__ db, int64_t n,
+                                                  unsigned long long *mu_key) {
+    __shared__ double sh[4];
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double v = 0.0;
+    if (i < n) {
+        const float *x = db + i * kDim;
+        double s = 0.0;
+        for (int j = 0; j < kDim; ++j) s = fma((double)x[j], (double)x[j], s);
+        v = sqrt(s);
+    }
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(mu_key, key_of(fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]))));
+}
+
+__global__ void zero_u64(unsigned long long *p, int count) {
+    if ((int)threadIdx.x < count) p[threadIdx.x] = 0ull;
+}
+
+// Window width for the exhaustive float32 scan: the true argmax has s~ no
+// lower than the scan maximum minus 2 (eps_f32 + eps_f64).
+struct BfPrepArgs {
+    const QNorm *qn;
+    const unsigned long long *mu_key;
+    int64_t q, q_pad;
+    float *win_scan;  // widened for the float32 subtraction in the scan
+    double *win;      // exact window for the re-filter
+    unsigned long long *best_key;
+    int32_t *best_idx, *cnt, *qflag;
+    unsigned long long *counter;
+};
+
+__global__ __launch_bounds__(256) void bf_prep(BfPrepArgs P) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) *P.counter = 0;
+    if (i >= P.q_pad) return;
+    if (i >= P.q) {
+        P.win_scan[i] = 0.0f;
+        return;
+    }
+    const double mu = sim_of_key(*P.mu_key) * (1.0 + ldexp(1.0, -40));
+    const QNorm qn = P.qn[i];
+    const double scale = qn.full * mu;
+    double w = 2.0 * (gamma_n(kDim, kU32) * scale + kDim * ldexp(1.0, -125) +
+                      gamma_n(kDim, kU64) * scale);
+    w = w * (1.0 + ldexp(1.0, -20)) + ldexp(1.0, -100);
+    P.win[i] = w;
+    P.win_scan[i] = __double2float_ru(w + ldexp(1.0, -22) * scale);
+    P.best_key[i] = 0ull;
+    P.best_idx[i] = kIdxNone;
+    P.cnt[i] = 0;
+    P.qflag[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void bf_threshold(const float *part_val, int32_t n_chunks,
+                                                    int32_t q_pad, int64_t q, const double *win,
+                                                    float *thr) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= q) return;
+    float m = -INFINITY;
+    for (int c = 0; c < n_chunks; ++c) m = fmaxf(m, part_val[(int64_t)c * q_pad + i]);
+    thr[i] = __double2float_rd((double)m - win[i]);
+}
+
+// Single-pass re-filter threshold: max(T_q, m - w_q) with m the final scan
+// maximum over all chunks (which includes the starting value T_q + w_q).
+__global__ __launch_bounds__(256) void win_threshold(const float *part_val, int32_t n_chunks,
+                                                     int32_t q_pad, int64_t q, const double *win,
+                                                     const float *thr, float *out) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= q) return;
+    float m = -INFINITY;
+    for (int c = 0; c < n_chunks; ++c) m = fmaxf(m, part_val[(int64_t)c * q_pad + i]);
+    out[i] = fmaxf(thr[i], __double2float_rd((double)m - win[i]));
+}
+
+__global__ void fill_lower(double *lower, int64_t *idx, int64_t q) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < q; i += (int64_t)gridDim.x * 256) {
+        lower[i] = -INFINITY;
+        idx[i] = -1;
+    }
+}
+
+// ---------------------------------------------------------- launch helpers
+
+unsigned blocks_for(int64_t items, int per = 256) {
+    return (unsigned)std::max<int64_t>(1, (items + per - 1) / per);
+}
+
+// precision 0: float32 stream of width w; 1: bf16 stream of width w.
+const char *scan_tag(int mode, int precision) {
+    static const char *const tags[4][3] = {
+        {"scan_argmax_f32", "scan_argmax_bf16", "scan_argmax_fp8"},
+        {"scan_filter_f32", "scan_filter_bf16", "scan_filter_fp8"},
+        {"scan_window_f32", "scan_window_bf16", "scan_window_fp8"},
+        {"scan_store_f32", "scan_store_bf16", "scan_store_fp8"}};
+    return tags[mode][precision == HN_PREC_FP32 ? 0 : (precision == HN_PREC_BF16 ? 1 : 2)];
+}
+
+template <int MODE>
+int launch_scan(int precision, int w, int cfg, const Plan &p, const ScanArgs &A,
+                hipStream_t s) {
+    ProfScope prof(s, scan_tag(MODE, precision));
+    int rc;
+    if (precision == HN_PREC_FP32)
+        rc = w <= 32 ? launch_scan_f32_narrow(MODE, w, cfg, p, A, s)
+                     : launch_scan_f32_wide(MODE, w, cfg, p, A, s);
+    else if (precision == HN_PREC_BF16)
+        rc = launch_scan_bf16(MODE, w, cfg, p, A, s);
+    else if (precision == HN_PREC_FP8)
+        rc = launch_scan_fp8(MODE, w, cfg, p, A, s);
+    else
+        return fail(HN_ERR_UNSUPPORTED, "precision %d is not available", precision);
+    if (rc) return fail(HN_ERR_INVALID_ARG, "no scan kernel for mode %d width %d config %d", MODE, w, cfg);
+    HN_HIP(hipGetLastError());
+    return HN_OK;
+}
+
+}  // namespace
+}  // namespace hn

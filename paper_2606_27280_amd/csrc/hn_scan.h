@@ -57,6 +57,8 @@ struct ScanArgs {
     int *redo;          // items to re-run (capacity n_items)
     unsigned *redo_count;  // zero before the launch
     const float *init_best;  // window: starting running maximum per query, or NULL
+    int32_t q_base;     // added to the query of every emitted pair (several
+                        // databases sharing one pair list and flag array)
 };
 
 // ------------------------------------------------------------ tile shapes
@@ -339,7 +341,7 @@ __device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B,
         for (int u = 0; u < 4; ++u) {
             if (pv[u]) {
                 const int pos = off + (int)lane_prefix(mv[u]);
-                B.pairs[pos] = make_int2(q, eblk + Tile::out_row(lane, v0 + u));
+                B.pairs[pos] = make_int2(A.q_base + q, eblk + Tile::out_row(lane, v0 + u));
                 if (WithVal) B.vals[pos] = a[v0 + u];
             }
             off += c[u];
@@ -358,9 +360,10 @@ __device__ __forceinline__ void lex_merge(float &v, int &i, float ov, int oi) {
 
 // ------------------------------------------------------------ the scan kernel
 
-// One work item: query block qb x entry chunk `chunk`.
+// One work item: query block qb x entry chunk `chunk`.  redo_id is what an
+// overflowing item records for its re-run (its index in the launch's list).
 template <class Tile, int NQ, int WQ, int MODE, bool Direct>
-__device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
+__device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, const int redo_id,
                                           float (*sh_val)[NQ * Tile::kCols],
                                           int (*sh_idx)[NQ * Tile::kCols], int *sh_full,
                                           EmitBuf &eb) {
@@ -512,7 +515,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item,
             if (!redo) {
                 flush_pairs<MODE == kWindow>(A, eb);
             } else if (threadIdx.x == 0) {
-                A.redo[atomicAdd(A.redo_count, 1u)] = item;
+                A.redo[atomicAdd(A.redo_count, 1u)] = redo_id;
             }
             eb.count = 0;
             eb.full = false;
@@ -585,7 +588,7 @@ __global__ __launch_bounds__(256) void scan_kernel(ScanArgs A) {
     const int per = (A.n_items + kXcds - 1) / kXcds;
     const int lo = x * per, hi = min(A.n_items, lo + per);
     for (int item = lo + w; item < hi; item += groups_per_xcd)
-        scan_item<Tile, NQ, WQ, MODE, false>(A, item, sh_val, sh_idx, sh_full, eb);
+        scan_item<Tile, NQ, WQ, MODE, false>(A, item, item, sh_val, sh_idx, sh_full, eb);
 }
 
 // Re-runs the items whose survivor buffers overflowed, flushing as it goes.
@@ -593,9 +596,50 @@ template <class Tile, int NQ, int WQ, int MODE>
 __global__ __launch_bounds__(256) void scan_redo_kernel(ScanArgs A) {
     HN_SCAN_SHARED(Tile, NQ, MODE)
     const unsigned n = __builtin_amdgcn_readfirstlane(*A.redo_count);
-    for (unsigned r = blockIdx.x; r < n; r += gridDim.x)
-        scan_item<Tile, NQ, WQ, MODE, true>(A, __builtin_amdgcn_readfirstlane(A.redo[r]), sh_val,
-                                            sh_idx, sh_full, eb);
+    for (unsigned r = blockIdx.x; r < n; r += gridDim.x) {
+        const int item = __builtin_amdgcn_readfirstlane(A.redo[r]);
+        scan_item<Tile, NQ, WQ, MODE, true>(A, item, item, sh_val, sh_idx, sh_full, eb);
+    }
+}
+
+// Several databases in one launch: items[i] = (database, its local item);
+// every database has its own arguments (same tile and configuration).  The
+// list is ordered database by database, chunk-major inside each, and split
+// into 8 XCD ranges as in scan_kernel.  Overflowing items record their list
+// index in the redo list every database of the launch shares.
+template <class Tile, int NQ, int WQ, int MODE>
+__global__ __launch_bounds__(256) void scan_multi_kernel(const ScanArgs *__restrict__ dbs,
+                                                         const int2 *__restrict__ items,
+                                                         int n_items) {
+    HN_SCAN_SHARED(Tile, NQ, MODE)
+    const int groups_per_xcd = (int)gridDim.x / kXcds;
+    const int x = (int)(blockIdx.x % kXcds), w = (int)(blockIdx.x / kXcds);
+    const int per = (n_items + kXcds - 1) / kXcds;
+    const int lo = x * per, hi = min(n_items, lo + per);
+    for (int item = lo + w; item < hi; item += groups_per_xcd) {
+        const int2 it = items[item];
+        const int d = __builtin_amdgcn_readfirstlane(it.x);
+        const int local = __builtin_amdgcn_readfirstlane(it.y);
+        const ScanArgs A = dbs[d];
+        scan_item<Tile, NQ, WQ, MODE, false>(A, local, item, sh_val, sh_idx, sh_full, eb);
+    }
+}
+
+template <class Tile, int NQ, int WQ, int MODE>
+__global__ __launch_bounds__(256) void scan_multi_redo_kernel(const ScanArgs *__restrict__ dbs,
+                                                              const int2 *__restrict__ items,
+                                                              const int *__restrict__ redo,
+                                                              const unsigned *redo_count) {
+    HN_SCAN_SHARED(Tile, NQ, MODE)
+    const unsigned n = __builtin_amdgcn_readfirstlane(*redo_count);
+    for (unsigned r = blockIdx.x; r < n; r += gridDim.x) {
+        const int item = __builtin_amdgcn_readfirstlane(redo[r]);
+        const int2 it = items[item];
+        const int d = __builtin_amdgcn_readfirstlane(it.x);
+        const int local = __builtin_amdgcn_readfirstlane(it.y);
+        const ScanArgs A = dbs[d];
+        scan_item<Tile, NQ, WQ, MODE, true>(A, local, item, sh_val, sh_idx, sh_full, eb);
+    }
 }
 
 // ------------------------------------------------------------ host side
@@ -745,6 +789,46 @@ inline int launch_tile(int mode, int cfg, const Plan &p, const ScanArgs &A, hipS
     return 1;
 }
 
+// Several databases in one launch (argmax and filter modes).  The grid is
+// sized by the occupancy of the single-database kernel of the same tile.
+template <class Tile, int MODE, int C>
+inline void launch_multi_one(const ScanArgs *dbs, const int2 *items, int n_items,
+                             const int *redo, const unsigned *redo_count, hipStream_t s) {
+    if constexpr (kCfgNQ[C] * tile_cost<Tile>() <= kTileBudget) {
+        hipLaunchKernelGGL((scan_multi_kernel<Tile, kCfgNQ[C], kCfgWQ[C], MODE>),
+                           dim3(persistent_grid<Tile, kCfgNQ[C], kCfgWQ[C], MODE>(n_items)),
+                           dim3(256), 0, s, dbs, items, n_items);
+        if constexpr (MODE == kFilter)
+            hipLaunchKernelGGL((scan_multi_redo_kernel<Tile, kCfgNQ[C], kCfgWQ[C], MODE>),
+                               dim3(256), dim3(256), 0, s, dbs, items, redo, redo_count);
+    }
+}
+
+template <class Tile>
+inline int launch_tile_multi(int mode, int cfg, const ScanArgs *dbs, const int2 *items,
+                             int n_items, const int *redo, const unsigned *redo_count,
+                             hipStream_t s) {
+    if (cfg < 0 || cfg >= kNumCfg || kCfgNQ[cfg] * tile_cost<Tile>() > kTileBudget) return 1;
+    if (mode != kArgmax && mode != kFilter) return 1;
+#define HN_MULTI_CASE(C)                                                   \
+    case C:                                                                \
+        if (mode == kArgmax)                                                           \
+            launch_multi_one<Tile, kArgmax, C>(dbs, items, n_items, redo, redo_count, s); \
+        else                                                                           \
+            launch_multi_one<Tile, kFilter, C>(dbs, items, n_items, redo, redo_count, s); \
+        return 0;
+    switch (cfg) {
+        HN_MULTI_CASE(0)
+        HN_MULTI_CASE(1)
+        HN_MULTI_CASE(2)
+        HN_MULTI_CASE(3)
+        HN_MULTI_CASE(4)
+        HN_MULTI_CASE(5)
+    }
+#undef HN_MULTI_CASE
+    return 1;
+}
+
 // Tile families: for each precision, a stream of width W up to 32 runs on the
 // 32x32 shape, wider streams on the 16x16 shape (fp8 streams are 16 or 32).  cost = tile_cost<Tile>().
 struct TileInfo {
@@ -769,5 +853,10 @@ int launch_scan_bf16(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
                      hipStream_t s);        // widths 16, 32 (32x32), 64, 128 (16x16)
 int launch_scan_fp8(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
                     hipStream_t s);         // widths 16, 32 (32x32)
+// Several databases of one stream width in one launch: float32 widths 8, 16,
+// 32; bf16 and fp8 widths 16, 32.  Nonzero if not compiled.
+int launch_scan_multi(int precision, int mode, int w, int cfg, const ScanArgs *dbs,
+                      const int2 *items, int n_items, const int *redo,
+                      const unsigned *redo_count, hipStream_t s);
 
 }  // namespace hn
