@@ -11,6 +11,13 @@ same queries, the pruned fraction, the dominant kernel's roofline fraction
 (kernel time from HIP events recorded on the library's stream during the
 timed steps) and the CPU oracle timed on a bounded sample.
 
+--workload 4: 64 databases (N_d log-uniform in [4096, 2^21], K_d in {8, 16},
+alpha_d in {1/32, 1/8}) with ragged query batches (Q_d log-uniform in
+[1, 4096]), searched as one multi-database plan replayed as a HIP graph;
+reports whole-set queries/s, the per-database batch latency p50/p99 (each
+batch alone through its own plan and graph), the same queries as sequential
+single-database calls, and exactness against them.
+
 Other workloads: --workload 3 (N = 4M, K = 8, alpha = 1/32, Q = 65,536; the
 precision form) and --workload 5 (N = 4M, K = 16, alpha = 1/8, Q = 65,536
 held-out queries; the seed model is built first, untimed: k-means++ anchors,
@@ -138,12 +145,155 @@ def cpu_baseline(db, qs, k, alpha, budget_s):
                       "branch-and-bound (Algorithm 1), %.1f s" % (done, len(qs), len(db), spent)}
 
 
+def gpu_time(fn, reps, torch):
+    """Seconds per call from HIP events on the current stream."""
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / 1e3 / reps
+
+
+def bench_batched(args):
+    """Workload 4: the multi-database plan against the same work as one call
+    per database."""
+    import numpy as np
+    import torch
+
+    import hn_inputs
+    import paper_2606_27280_amd as hn
+    from paper_2606_27280_amd import accounting as acc
+    from paper_2606_27280_amd.autotune import Tuner
+
+    specs = hn_inputs.batched_set()
+    dev = torch.device("cuda:0")
+    ixs, qlist, flops = [], [], 0.0
+    t0 = time.perf_counter()
+    for t, sp in enumerate(specs):
+        db = sp.db()
+        qs = sp.queries(db)
+        ixs.append(hn.Index(torch.from_numpy(db).to(dev), sp.k, sp.alpha))
+        qlist.append(qs)
+        flops += acc.scan_flops(sp.q, sp.n, sp.k)
+        if t % 8 == 7:
+            log("built %d / %d databases (%.0f s)" % (t + 1, len(specs), time.perf_counter() - t0))
+    counts = [len(q) for q in qlist]
+    Q = sum(counts)
+    N = sum(sp.n for sp in specs)
+    dq = torch.from_numpy(np.concatenate(qlist)).to(dev)
+    log("%d databases, %d entries, %d queries" % (len(specs), N, Q))
+
+    tuner = Tuner()
+    qt, cb = args.query_tiles, args.chunk_blocks
+    tuned = None
+    if qt == 0 and cb == 0:
+        best, table = tuner.tune_multi(ixs, counts, dq, precision=args.precision, log=log)
+        qt, cb = best
+        tuned = {"%d,%d" % k: round(v, 4) for k, v in table.items()}
+    plan = hn.MultiPlan(ixs, counts, precision=args.precision, query_tiles=qt, chunk_blocks=cb)
+    idx = torch.empty(Q, dtype=torch.int64, device=dev)
+    sim = torch.empty(Q, dtype=torch.float64, device=dev)
+
+    def step():
+        plan.search(dq, use_graph=True, out=(idx, sim))
+
+    for _ in range(args.warmup):
+        step()
+    sec = gpu_time(step, args.steps, torch)
+    qps = Q / sec
+    log("multi plan (graph): %.3f ms per set, %.0f queries/s" % (1e3 * sec, qps))
+    # kernel times of one eager pass
+    with hn.profile() as prof:
+        plan.search(dq, use_graph=False)
+    kernels = {k: {"avg_ms": round(v["ms"] / v["launches"], 4), "launches": v["launches"]}
+               for k, v in prof.result.items()}
+    dom = max((k for k in prof.result if "scan" in k), key=lambda k: prof.result[k]["ms"])
+    dom_s = prof.result[dom]["ms"] / 1e3
+    peak = PEAK[{"fp32": "fp32_mfma_tflops", "bf16": "bf16_mfma_tflops",
+                 "fp8": "fp8_mfma_tflops"}[args.precision]]
+    achieved = flops / dom_s / 1e12
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "algorithmic": "sum over databases of 2*Q_d*N_d*K_d = %.4g flop per scan pass, "
+                               "all launches of the pass" % flops}
+    # the same queries one call per database (eager), and exactness
+    outs = []
+
+    def singles():
+        outs.clear()
+        for ix, q0, c in zip(ixs, np.cumsum([0] + counts[:-1]), counts):
+            if c:
+                outs.append(ix.search(dq[q0:q0 + c], precision=args.precision))
+
+    singles()
+    s_idx = torch.cat([o[0] for o in outs])
+    s_sim = torch.cat([o[1] for o in outs])
+    exact = bool(torch.equal(s_idx, idx) and torch.equal(s_sim, sim))
+    ssec = gpu_time(singles, max(1, args.steps // 2), torch)
+    log("one call per database: %.3f ms per set; identical=%s" % (1e3 * ssec, exact))
+    # per-batch latency: each database's batch alone, own plan, graph
+    lat = []
+    for ix, q0, c in zip(ixs, np.cumsum([0] + counts[:-1]), counts):
+        if not c:
+            continue
+        p1 = hn.MultiPlan([ix], [c], precision=args.precision, query_tiles=qt, chunk_blocks=cb)
+        sub = dq[q0:q0 + c].contiguous()
+        o1 = (torch.empty(c, dtype=torch.int64, device=dev),
+              torch.empty(c, dtype=torch.float64, device=dev))
+        p1.search(sub, out=o1)
+        lat.append(gpu_time(lambda: p1.search(sub, out=o1), 5, torch))
+        p1.close()
+    lat = np.array(lat) * 1e3
+    res = {
+        "metric": METRIC,
+        "value": round(qps, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * sec, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "hn_batched_64db", "databases": len(specs), "entries": N,
+                   "queries": Q, "n_range": [min(sp.n for sp in specs), max(sp.n for sp in specs)],
+                   "q_range": [min(counts), max(counts)], "k": sorted({sp.k for sp in specs}),
+                   "alpha": sorted({sp.alpha for sp in specs}), "precision": args.precision,
+                   "seed": "plain", "rescoring": "f64", "query_tiles": qt, "chunk_blocks": cb,
+                   "graph": True},
+        "plan": plan.info(),
+        "roofline": roofline,
+        "kernels": kernels,
+        "per_batch_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                                 "p99": round(float(np.percentile(lat, 99)), 4),
+                                 "max": round(float(lat.max()), 4), "batches": int(len(lat))},
+        "sequential_calls": {"queries_per_s": round(Q / ssec, 1), "ms_per_set": round(1e3 * ssec, 4)},
+        "speedup_vs_sequential": round(ssec / sec, 2),
+        "exact_vs_single": exact,
+    }
+    if tuned is not None:
+        res["autotune_ms"] = tuned
+    print(json.dumps(res), flush=True)
+    plan.close()
+    for ix in ixs:
+        ix.close()
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == 4:
+        bench_batched(args)
+        return
     import numpy as np
     import torch
 

@@ -97,7 +97,8 @@ typedef struct {
                              0 = tuned */
     int64_t survivor_cap; /* capacity of the survivor list in (query, entry)
                              pairs; 0 = automatic.  Queries whose survivors
-                             do not fit are finished by an exact fallback. */
+                             do not fit are finished exactly by a second
+                             pass (see hn_search_top1). */
     double beta;          /* < 0: exact search (bound alpha).  0 <= beta <
                              alpha: soft mode of Section 7, which replaces
                              alpha by beta in the skip test and is no longer
@@ -156,7 +157,11 @@ int hn_index_info(const hn_index *ix, int64_t *n, int32_t *k, double *alpha,
  *   queries  device, float32 [q][128]; q >= 0 (q = 0 is a no-op).
  *   out_idx  device, int64 [q];  out_sim  device, double [q].
  *   opts     NULL = defaults.  aux, stats: NULL allowed; a non-NULL stats
- *            makes the call synchronise `stream`.
+ *            makes the call synchronise `stream`, and so do the fp8 scan and
+ *            the single-pass seeds (once per query batch): their queries whose
+ *            survivors overflow the pair list are searched again by a float32
+ *            filter pass seeded with the best candidate they reached.  Other
+ *            forms finish such queries with an exhaustive float64 pass.
  * A query with a non-finite component gets idx -1 and sim NaN.
  */
 int hn_search_top1(const hn_index *ix, const float *queries, int64_t q, int64_t *out_idx,

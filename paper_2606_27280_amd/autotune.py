@@ -17,6 +17,8 @@ import time
 
 QUERY_TILES = (1, 2, 4, 8)
 CHUNK_BLOCKS = (0, 16, 32, 64, 128, 256)
+MULTI_QUERY_TILES = (1, 2, 4)
+MULTI_CHUNK_BLOCKS = (0, 16, 64)
 
 
 def _bucket(v: int) -> int:
@@ -86,6 +88,50 @@ class Tuner:
         k = self.key(dev_name, index.n, index.k, precision, queries.shape[0])
         self.table[k] = {"query_tiles": best[0], "chunk_blocks": best[1],
                          "ms": results[best], "when": time.time()}
+        if save:
+            self.save()
+        return best, results
+
+    def tune_multi(self, indexes, q_counts, queries, precision="fp32",
+                   query_tiles=MULTI_QUERY_TILES, chunk_blocks=MULTI_CHUNK_BLOCKS, reps=3,
+                   save=True, log=None):
+        """The same search for a multi-database plan: every candidate shape
+        becomes a plan, replayed as a HIP graph and timed with HIP events;
+        all must return bit-identical results.  Returns (best, table)."""
+        import torch
+
+        import paper_2606_27280_amd as hn
+        dev_name = torch.cuda.get_device_name(queries.device)
+        ref = None
+        results = {}
+        for qt in query_tiles:
+            for cb in chunk_blocks:
+                plan = hn.MultiPlan(indexes, q_counts, precision=precision, query_tiles=qt,
+                                    chunk_blocks=cb)
+                idx, sim = plan.search(queries, use_graph=True)
+                if ref is None:
+                    ref = (idx.clone(), sim.clone())
+                elif not (torch.equal(idx, ref[0]) and torch.equal(sim, ref[1])):
+                    plan.close()
+                    raise RuntimeError("shape (%d, %d) changed the results" % (qt, cb))
+                torch.cuda.synchronize()
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(reps):
+                    plan.search(queries, use_graph=True, out=(idx, sim))
+                b.record()
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(b) / reps
+                plan.close()
+                results[(qt, cb)] = ms
+                if log:
+                    log("tune multi %s qt=%d cb=%d: %.4f ms" % (precision, qt, cb, ms))
+        best = min(results, key=results.get)
+        k = "multi|%s|%s|db%d|q%d" % (dev_name, precision, len(indexes),
+                                      _bucket(int(sum(q_counts))))
+        self.table[k] = {"query_tiles": best[0], "chunk_blocks": best[1], "ms": results[best],
+                         "when": time.time()}
         if save:
             self.save()
         return best, results

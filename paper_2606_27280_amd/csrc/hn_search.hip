@@ -485,12 +485,15 @@ int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *o
     return HN_OK;
 }
 
-// A single-pass batch, then its overflowing queries again as a plain filter
-// pass seeded with the best candidate each reached (exact: every entry that
-// can beat that candidate survives the filter; the candidate is the seed).
-int single_pass_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *out_idx,
-                      double *out_sim, const hn_search_opts &o, const hn_search_aux *aux,
-                      hn_search_stats *stats, hipStream_t s) {
+// A batch whose survivor list may overflow (the single-pass forms and the
+// fp8 scan, whose slack keeps many more pairs), then its overflowing queries
+// again as a plain float32 filter pass seeded with the best candidate each
+// reached (exact: every entry that can beat that candidate survives the
+// filter, and the candidate is the seed).  Synchronises once to learn the
+// number of such queries.
+int rerun_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *out_idx,
+                double *out_sim, const hn_search_opts &o, const hn_search_aux *aux,
+                hn_search_stats *stats, hipStream_t s) {
     Arena *ar = nullptr;
     int rc = arena_for((void *)s, (size_t)q * (4 + 8 + 8 + 8 + 8 + kDim * 4) + 8 * 256, &ar, 2);
     if (rc) return rc;
@@ -508,6 +511,7 @@ int single_pass_batch(const hn_index *ix, const float *queries, int64_t q, int64
                        ov.list, ov.n, sub_q);
     hn_search_opts o2 = o;
     o2.seed = HN_SEED_PLAIN;
+    o2.precision = HN_PREC_FP32;
     o2.survivor_cap = 0;
     rc = search_batch(ix, sub_q, ov.n, sub_idx, sub_sim, o2, nullptr, nullptr, s, ov.lower,
                       ov.lower_idx, nullptr);
@@ -550,12 +554,12 @@ extern "C" int hn_search_top1(const hn_index *ix, const float *queries, int64_t 
             a2.slack = aux->slack ? aux->slack + q0 : nullptr;
         }
         hn_search_stats st{0, 0};
-        if (o.seed == HN_SEED_PLAIN)
+        if (o.seed == HN_SEED_PLAIN && o.precision != HN_PREC_FP8)
             rc = search_batch(ix, queries + q0 * kDim, nb, out_idx + q0, out_sim + q0, o,
                               aux ? &a2 : nullptr, stats ? &st : nullptr, s);
         else
-            rc = single_pass_batch(ix, queries + q0 * kDim, nb, out_idx + q0, out_sim + q0, o,
-                                   aux ? &a2 : nullptr, stats ? &st : nullptr, s);
+            rc = rerun_batch(ix, queries + q0 * kDim, nb, out_idx + q0, out_sim + q0, o,
+                             aux ? &a2 : nullptr, stats ? &st : nullptr, s);
         if (rc) return rc;
         if (stats) {
             stats->survivors += st.survivors;

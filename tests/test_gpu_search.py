@@ -398,3 +398,14 @@ def test_workload2_full_size_sampled(hn):
     say("workload2: pruned %.4f%%, survivors/query %.1f" % (100 * pruned, surv.mean()))
     assert pruned > 0.99
     ix.close()
+
+
+def test_fp8_overflow_rerun_exact(hn):
+    """fp8 scans keep many more pairs; a list far too small sends the
+    overflowing queries through a float32 filter pass seeded with the best
+    candidate each reached."""
+    w = hn_inputs.workload(1)
+    db = w.db()
+    qs = w.queries(db)
+    ref, aux, st = _check_search(hn, db, qs, w.k, w.alpha, "fp8", "fp8-rerun", survivor_cap=700)
+    assert st["overflow_queries"] > 0
