@@ -414,6 +414,7 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
         S.part_idx = part_idx + part_off[d];
         S.n_chunks = p.n_chunks;
         S.q_pad = (int32_t)p.q_pad;
+        S.part_ld = (int32_t)p.q_pad;
         S.shape = 32;
         S.group_size = 16;
         S.queries = P->q_buf + pad_base[d] * kDim;

@@ -127,6 +127,7 @@ struct SeedArgs {
     const float *part_val;
     const int32_t *part_idx;
     int32_t n_chunks, q_pad;
+    int32_t part_ld;            // row stride of the partials (the argmax scan's q_pad)
     int32_t shape, group_size;  // scan tile shape (16 or 32) and entries per lane group
     const float *queries;
     int64_t q;
@@ -219,8 +220,8 @@ __device__ __forceinline__ void seed_one(const SeedArgs &S, const int64_t i, con
         float bv = -INFINITY;
         int bi = -1;
         for (int c = lane; c < S.n_chunks; c += 64)
-            lex_merge(bv, bi, S.part_val[(int64_t)c * S.q_pad + i],
-                      S.part_idx[(int64_t)c * S.q_pad + i]);
+            lex_merge(bv, bi, S.part_val[(int64_t)c * S.part_ld + i],
+                      S.part_idx[(int64_t)c * S.part_ld + i]);
         for (int o = 32; o > 0; o >>= 1) {
             const float ov = __shfl_xor(bv, o);
             const int oi = __shfl_xor(bi, o);

@@ -17,7 +17,9 @@ struct Work {
     int cfg = 0;
     int precision = HN_PREC_FP32;
     int width = 0;
-    int shape = 16;  // tile shape of the scan (16 or 32): decodes argmax groups
+    Plan seed_plan;  // the argmax (seed) scan: bf16 stream
+    int seed_cfg = 0;
+    int shape = 16;  // tile shape of the argmax scan (16 or 32): decodes its groups
     const void *stream_x = nullptr;
     float *op32 = nullptr;
     uint16_t *op16 = nullptr;
@@ -48,12 +50,12 @@ const void *operands_of(const Work &W) {
                                          : (const void *)W.op8;
 }
 
-void launch_prep(const hn_index *ix, const float *queries, int64_t q, const Plan &p, Work &W,
+void launch_prep(const hn_index *ix, const float *queries, int64_t q, int64_t q_pad, Work &W,
                  hipStream_t s) {
     PrepArgs P;
     P.q = queries;
     P.nq = q;
-    P.q_pad = p.q_pad;
+    P.q_pad = q_pad;
     P.k = ix->k;
     P.w32 = ix->kp;
     P.w16 = ix->kb;
@@ -64,7 +66,7 @@ void launch_prep(const hn_index *ix, const float *queries, int64_t q, const Plan
     P.qn = W.qn;
     P.work = W.work;
     ProfScope prof_(s, "prep_queries");
-    hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(prep_queries, dim3(blocks_for(q_pad)), dim3(256), 0, s, P);
 }
 
 int validate_opts(const hn_index *ix, const hn_search_opts *o) {
@@ -101,19 +103,32 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
         return fail(HN_ERR_INVALID_ARG, "query_tiles=%d is not available for this width",
                     o.query_tiles);
     W.plan = make_plan(ix->n, q, W.cfg, o.chunk_blocks, ti.rows, ti.cols);
-    W.shape = ti.rows;
     const Plan &p = W.plan;
+    // The argmax (seed) scan runs on the bf16 copy whatever the filter's
+    // precision: the seed only has to be a real entry with a near-maximal
+    // score (its float64 sim is the bound), and bf16 contracts four times
+    // faster than float32 on the matrix cores.
+    const TileInfo tis = tile_info(HN_PREC_BF16, ix->kb);
+    W.seed_cfg = pick_cfg(q, tis.cols, tis.cost, o.query_tiles);
+    if (W.seed_cfg < 0)
+        return fail(HN_ERR_INVALID_ARG, "query_tiles=%d is not available for this width",
+                    o.query_tiles);
+    W.seed_plan = make_plan(ix->n, q, W.seed_cfg, o.chunk_blocks, tis.rows, tis.cols);
+    W.shape = tis.rows;
+    const Plan &sp = W.seed_plan;
+    const int64_t qp = std::max(p.q_pad, sp.q_pad);
+    const size_t part = std::max((size_t)p.n_chunks * p.q_pad, (size_t)sp.n_chunks * sp.q_pad);
     W.cap = cap;
 
     size_t bytes = 0;
     auto add = [&](size_t count, size_t sz) { bytes += (count * sz + 255) & ~size_t(255); };
-    add(p.q_pad * ix->kp, 4);
-    add(p.q_pad * ix->kb, 2);
-    add(p.q_pad * ix->k8, 1);
-    add(p.q_pad, sizeof(QNorm));
-    add((size_t)p.n_chunks * p.q_pad, 4);
-    add((size_t)p.n_chunks * p.q_pad, 4);
-    add(p.q_pad, 4);
+    add(qp * ix->kp, 4);
+    add(qp * ix->kb, 2);
+    add(qp * ix->k8, 1);
+    add(qp, sizeof(QNorm));
+    add(part, 4);
+    add(part, 4);
+    add(qp, 4);
     add(q, 4);
     add(q, 8);
     add(q, 8);
@@ -128,9 +143,9 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     add(cap, sizeof(int2));
     add(cap, 8);
     if (window) {
-        add(p.q_pad, 8);
-        add(p.q_pad, 4);
-        add(p.q_pad, 4);
+        add(qp, 8);
+        add(qp, 4);
+        add(qp, 4);
         add(q, 4);
         add(cap, 4);
         add(q, 8);
@@ -139,13 +154,13 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     Arena *ar = nullptr;
     int rc = arena_for((void *)s, bytes, &ar);
     if (rc) return rc;
-    W.op32 = ar->take<float>(p.q_pad * ix->kp);
-    W.op16 = ar->take<uint16_t>(p.q_pad * ix->kb);
-    W.op8 = ix->k8 ? ar->take<uint8_t>(p.q_pad * ix->k8) : nullptr;
-    W.qn = ar->take<QNorm>(p.q_pad);
-    W.part_val = ar->take<float>((size_t)p.n_chunks * p.q_pad);
-    W.part_idx = ar->take<int32_t>((size_t)p.n_chunks * p.q_pad);
-    W.thr = ar->take<float>(p.q_pad);
+    W.op32 = ar->take<float>(qp * ix->kp);
+    W.op16 = ar->take<uint16_t>(qp * ix->kb);
+    W.op8 = ix->k8 ? ar->take<uint8_t>(qp * ix->k8) : nullptr;
+    W.qn = ar->take<QNorm>(qp);
+    W.part_val = ar->take<float>(part);
+    W.part_idx = ar->take<int32_t>(part);
+    W.thr = ar->take<float>(qp);
     W.thr32 = ar->take<float>(q);
     W.seed_idx = ar->take<int64_t>(q);
     W.seed_sim = ar->take<double>(q);
@@ -161,16 +176,16 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     W.pairs = ar->take<int2>(cap);
     W.psim = ar->take<double>(cap);
     if (window) {
-        W.win = ar->take<double>(p.q_pad);
-        W.win_scan = ar->take<float>(p.q_pad);
-        W.init_best = ar->take<float>(p.q_pad);
+        W.win = ar->take<double>(qp);
+        W.win_scan = ar->take<float>(qp);
+        W.init_best = ar->take<float>(qp);
         W.thr_ref = ar->take<float>(q);
         W.pair_val = ar->take<float>(cap);
         W.lower = ar->take<double>(q);
         W.lower_idx = ar->take<int64_t>(q);
     }
 
-    launch_prep(ix, queries, q, p, W, s);
+    launch_prep(ix, queries, q, qp, W, s);
     HN_HIP(hipGetLastError());
     if (window) {
         if (o.seed == HN_SEED_LEARNED) {
@@ -184,26 +199,26 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
         lower_idx = W.lower_idx;
     }
 
-    ScanArgs A;
-    memset(&A, 0, sizeof A);
-    A.x = W.stream_x;
-    A.x_stride = W.width;
-    A.qs = operands_of(W);
-    A.q_stride = W.width;
-    A.n = ix->n;
-    A.n_blocks = p.n_blocks;
-    A.chunk_blocks = p.chunk_blocks;
-    A.n_chunks = p.n_chunks;
-    A.n_qb = p.n_qb;
-    A.n_items = p.n_items;
-    A.q_count = (int32_t)q;
-    A.q_pad = (int32_t)p.q_pad;
-    A.part_val = W.part_val;
-    A.part_idx = W.part_idx;
-    A.redo = W.redo;
-    A.redo_count = W.work + 2 * kXcds;
     if (!lower) {
-        rc = launch_scan<kArgmax>(W.precision, W.width, W.cfg, p, A, s);
+        ScanArgs A;
+        memset(&A, 0, sizeof A);
+        A.x = ix->major16;
+        A.x_stride = ix->kb;
+        A.qs = W.op16;
+        A.q_stride = ix->kb;
+        A.n = ix->n;
+        A.n_blocks = sp.n_blocks;
+        A.chunk_blocks = sp.chunk_blocks;
+        A.n_chunks = sp.n_chunks;
+        A.n_qb = sp.n_qb;
+        A.n_items = sp.n_items;
+        A.q_count = (int32_t)q;
+        A.q_pad = (int32_t)sp.q_pad;
+        A.part_val = W.part_val;
+        A.part_idx = W.part_idx;
+        A.redo = W.redo;
+        A.redo_count = W.work + 2 * kXcds;
+        rc = launch_scan<kArgmax>(HN_PREC_BF16, ix->kb, W.seed_cfg, sp, A, s);
         if (rc) return rc;
     }
 
@@ -211,8 +226,9 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     memset(&S, 0, sizeof S);
     S.part_val = W.part_val;
     S.part_idx = W.part_idx;
-    S.n_chunks = p.n_chunks;
-    S.q_pad = (int32_t)p.q_pad;
+    S.n_chunks = sp.n_chunks;
+    S.q_pad = (int32_t)qp;
+    S.part_ld = (int32_t)sp.q_pad;
     S.shape = W.shape;
     S.group_size = W.shape == 16 ? 4 : 16;
     S.queries = queries;
@@ -249,7 +265,7 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     S.counter = W.counter;
     {
         ProfScope prof_(s, "seed");
-        hipLaunchKernelGGL(seed_kernel, dim3(blocks_for(p.q_pad, 4)), dim3(256), 0, s, S);
+        hipLaunchKernelGGL(seed_kernel, dim3(blocks_for(qp, 4)), dim3(256), 0, s, S);
     }
     HN_HIP(hipGetLastError());
     return HN_OK;
@@ -633,7 +649,7 @@ extern "C" int hn_scan_scores(const hn_index *ix, const float *queries, int64_t 
     W.qn = ar->take<QNorm>(p.q_pad);
     W.work = ar->take<unsigned>(kWorkWords);
     W.redo = ar->take<int>(p.n_items);
-    launch_prep(ix, queries, q, p, W, s);
+    launch_prep(ix, queries, q, p.q_pad, W, s);
     ScanArgs A;
     memset(&A, 0, sizeof A);
     A.x = stream_of(ix, precision);
