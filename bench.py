@@ -44,6 +44,10 @@ PEAK = {  # MI355X published dense peaks
 
 
 ARGS = None
+# HBM traffic of a kernel measured with rocprofv3 counters (FETCH_SIZE and
+# WRITE_SIZE, copy-calibrated), recorded in profiles/ with a hash of the
+# kernel's sources; reported only while the sources still hash the same.
+TRAFFIC_SOURCES = {"scan_filter_f32": ("hn_internal.h", "hn_scan.h", "hn_scan_f32n.hip")}
 
 
 def log(*a):
@@ -70,7 +74,46 @@ def parse():
     ap.add_argument("--epochs", type=int, default=4, help="seed-model training epochs")
     ap.add_argument("--batch", type=int, default=1024, help="seed-model training batch")
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB 5 times (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+def measured_traffic(kernel, workload):
+    import glob
+    import hashlib
+    import re
+    srcs = TRAFFIC_SOURCES.get(kernel)
+    if not srcs:
+        return None
+    h = hashlib.sha256()
+    for f in srcs:
+        with open(os.path.join(ROOT, "paper_2606_27280_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()[:16]
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        with open(path) as fh:
+            for line in fh:
+                m = re.match(r"machine-readable: kernel=(\S+) workload=(\S+) "
+                             r"traffic_bytes_per_launch=(\d+) source_sha=(\S+)", line)
+                if m and m.group(1) == kernel and m.group(2) == workload and m.group(4) == sha:
+                    return int(m.group(3))
+    return None
+
+
+def copy_probe(mib):
+    """A plain copy kernel of known size for counter calibration: 5 copies of
+    mib MiB (torch's device copy)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_mib": mib, "copies": 5, "bytes_read_per_copy": n * 4,
+                      "bytes_written_per_copy": n * 4}), flush=True)
 
 
 def build_seed_model(hn, ix, w, db, dev, torch):
@@ -291,6 +334,9 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.workload == 4:
         bench_batched(args)
         return
@@ -350,7 +396,10 @@ def main():
                  "fp8": "fp8_mfma_tflops"}[dom.rsplit("_", 1)[1]]]
     achieved = flops / avg_s / 1e12
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic(dom, w.name) if per_step == 1 else None,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                "copy-calibrated)",
                 "algorithmic": "2*Q*N*K / %d launches per step = %.4g flop per launch" % (
                     per_step, flops)}
 
