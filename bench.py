@@ -74,6 +74,12 @@ def parse():
     ap.add_argument("--epochs", type=int, default=4, help="seed-model training epochs")
     ap.add_argument("--batch", type=int, default=1024, help="seed-model training batch")
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--beta-sweep", action="store_true",
+                    help="also time the soft mode (Section 7) at beta = alpha x {3/4, 1/2, "
+                         "1/4, 0}: recall@1 against the exact result and pruned fraction")
+    ap.add_argument("--layer", type=int, default=0, metavar="ROWS",
+                    help="only time the HN layer (Eq. 1) forward and backward on ROWS rows "
+                         "and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -100,6 +106,36 @@ def measured_traffic(kernel, workload):
                 if m and m.group(1) == kernel and m.group(2) == workload and m.group(4) == sha:
                     return int(m.group(3))
     return None
+
+
+def bench_layer(rows, steps, warmup):
+    """The HN layer on `rows` random float32 rows (K = 16, alpha = 1/8):
+    HBM-bound, 1 KiB per row forward (read + write), 1.5 KiB backward."""
+    import torch
+
+    import paper_2606_27280_amd as hn
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(7)
+    f = torch.randn((rows, 128), generator=g, device="cuda:0", dtype=torch.float32)
+    gr = torch.randn((rows, 128), generator=g, device="cuda:0", dtype=torch.float32)
+    res = {}
+    for name, fn, nbytes in (("forward", lambda: hn.hn_layer(f, 16, 0.125), rows * 1024),
+                             ("backward", lambda: hn.hn_layer_backward(f, gr, 16, 0.125),
+                              rows * 1536)):
+        for _ in range(warmup):
+            fn()
+        sec = gpu_time(fn, steps, torch)
+        gbs = nbytes / sec / 1e9
+        res[name] = {"ms": round(1e3 * sec, 4), "rows_per_s": round(rows / sec, 1),
+                     "achieved_gbs": round(gbs, 1), "frac_hbm": round(gbs / PEAK["hbm_gbs"], 4)}
+    print(json.dumps({"metric": "HN layer rows/s (Eq. 1 forward, VJP backward)",
+                      "value": res["forward"]["rows_per_s"], "unit": "rows/s", "n_gpus": 1,
+                      "steps": steps, "warmup": warmup, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "hn_layer", "rows": rows, "d": 128, "k": 16,
+                                 "alpha": 0.125},
+                      "roofline": {"bound": "hbm", "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                                   "forward": res["forward"], "backward": res["backward"]}}),
+          flush=True)
 
 
 def copy_probe(mib):
@@ -337,6 +373,9 @@ def main():
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
+    if args.layer:
+        bench_layer(args.layer, args.steps, args.warmup)
+        return
     if args.workload == 4:
         bench_batched(args)
         return
@@ -442,6 +481,21 @@ def main():
                           args.steps, 2, torch)
             forms[prec] = round(Q * args.steps / s2, 1)
         log("forms: %s" % forms)
+    beta_sweep = []
+    if args.beta_sweep:
+        # the exact result of this run is the reference for recall
+        for frac in (1.0, 0.75, 0.5, 0.25, 0.0):
+            beta = frac * w.alpha
+            kwb = dict(kw, beta=beta)
+            bi, bs, ba = ix.search(d_q, aux=True, **kwb)
+            recall = float((bi == idx).double().mean())
+            tb, _ = timed(lambda: ix.search(d_q, out=(bi, bs), **kwb), args.steps, 1, torch)
+            beta_sweep.append({"beta": beta, "beta_over_alpha": frac,
+                               "queries_per_s": round(Q * args.steps / tb, 1),
+                               "recall_at_1": round(recall, 5),
+                               "pruned_pct": round(float(
+                                   100.0 * (1.0 - ba["survivors"].double().mean() / w.n)), 4)})
+        log("beta sweep: %s" % beta_sweep)
     seed_forms = {}
     if seed_report is not None:
         # every seed form at the timed precision: queries/s, first-pass
@@ -489,6 +543,8 @@ def main():
     if seed_report is not None:
         res["seed_model"] = seed_report
         res["seed_forms"] = seed_forms
+    if beta_sweep:
+        res["beta_sweep"] = beta_sweep
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(db, qs, w.k, w.alpha, args.cpu_seconds)

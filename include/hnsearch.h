@@ -283,6 +283,26 @@ int hn_seed_labels(const hn_index *ix, const int64_t *anchors, int32_t n_anchor,
 int hn_set_seed_model(hn_index *ix, const float *params, const int64_t *anchors,
                       int32_t n_anchor, void *stream);
 
+/* ---------------------------------------------------------------- HN layer
+ * Eq. 1 (Section 3.1) as a batched layer and its vector-Jacobian product:
+ * the step that places embeddings on the split sphere before they are
+ * indexed.  Rows are float32 [b][128]; block norms in float64; every output
+ * rounded once to float32. */
+
+/* out[r] = ( sqrt(1-alpha) f[r,:k] / ||f[r,:k]||, sqrt(alpha) f[r,k:] /
+ * ||f[r,k:]|| ); at alpha = 0 the minor block is 0.  A block that cannot be
+ * normalised (zero, or a non-finite component in the row) comes out 0 and
+ * status[r] (int32 [b], may be NULL) says why: 0 ok, 1 zero major block,
+ * 2 zero minor block with alpha > 0, 3 non-finite component. */
+int hn_layer_forward(const float *f, int64_t b, int32_t d, int32_t k, double alpha, float *out,
+                     int32_t *status, void *stream);
+
+/* grad[r] = (dL/dout[r]) . d out[r] / d f[r] given g = dL/dout: per block of
+ * norm scale c, (c / ||u||) (g - v (v . g)) with u the block of f and
+ * v = u / ||u||; 0 for blocks that cannot be normalised. */
+int hn_layer_backward(const float *f, const float *g, int64_t b, int32_t d, int32_t k,
+                      double alpha, float *grad, void *stream);
+
 /* ---------------------------------------------------------- many databases
  * Ragged query batches against many indexes in one search: every scan is a
  * single persistent launch over the work items of all databases of one stream

@@ -17,7 +17,8 @@ from ._lib import (HN_BUILD_LOW_PRECISION, HN_BUILD_NO_VALIDATE, HN_MLP_PARAMS, 
 __all__ = ["Index", "bruteforce_top1", "profile", "HNError", "PRECISIONS", "SEEDS",
            "HN_PREC_FP32", "HN_PREC_BF16", "HN_PREC_FP8", "HN_SEED_PLAIN", "HN_SEED_LEARNED",
            "HN_SEED_WINDOW", "HN_BUILD_NO_VALIDATE", "HN_BUILD_LOW_PRECISION", "HN_MLP_PARAMS",
-           "mlp_forward", "mlp_grad", "mlp_adamw", "seed_train", "MultiPlan"]
+           "mlp_forward", "mlp_grad", "mlp_adamw", "seed_train", "MultiPlan", "hn_layer",
+           "hn_layer_backward"]
 
 PRECISIONS = {"fp32": HN_PREC_FP32, "bf16": HN_PREC_BF16, "fp8": HN_PREC_FP8}
 SEEDS = {"plain": HN_SEED_PLAIN, "learned": HN_SEED_LEARNED, "window": HN_SEED_WINDOW}
@@ -243,6 +244,29 @@ class MultiPlan:
             self.close()
         except Exception:
             pass
+
+
+def hn_layer(f, k, alpha, status=False, stream=None):
+    """Eq. 1 on a batch (hn_layer_forward): float32 [b][128] out, plus the
+    int32 row status when asked."""
+    torch = _torch()
+    fp = _dev(f, torch.float32, "f", 2)
+    out = torch.empty_like(f)
+    st = torch.empty(f.shape[0], dtype=torch.int32, device=f.device) if status else None
+    _lib.check(_lib.lib().hn_layer_forward(fp, f.shape[0], f.shape[1], int(k), float(alpha),
+                                           _ptr(out), _ptr(st), _stream(stream)))
+    return (out, st) if status else out
+
+
+def hn_layer_backward(f, g, k, alpha, stream=None):
+    """Vector-Jacobian product of Eq. 1 (hn_layer_backward)."""
+    torch = _torch()
+    fp = _dev(f, torch.float32, "f", 2)
+    gp = _dev(g, torch.float32, "g", 2)
+    out = torch.empty_like(f)
+    _lib.check(_lib.lib().hn_layer_backward(fp, gp, f.shape[0], f.shape[1], int(k), float(alpha),
+                                            _ptr(out), _stream(stream)))
+    return out
 
 
 def _adamw(lr, beta1, beta2, eps, weight_decay):

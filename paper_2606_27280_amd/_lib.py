@@ -79,6 +79,8 @@ SIGNATURES = {
     "hn_kmeanspp": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "hn_seed_labels": (_i32, [_vp, _vp, _i32, _vp, _i64, _vp, _vp]),
     "hn_set_seed_model": (_i32, [_vp, _vp, _vp, _i32, _vp]),
+    "hn_layer_forward": (_i32, [_vp, _i64, _i32, _i32, _dbl, _vp, _vp, _vp]),
+    "hn_layer_backward": (_i32, [_vp, _vp, _i64, _i32, _i32, _dbl, _vp, _vp]),
     "hn_multi_plan_create": (_i32, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_i64),
                                     ctypes.POINTER(SearchOpts), ctypes.POINTER(_vp)]),
     "hn_multi_search": (_i32, [_vp, _vp, _vp, _vp, _i32, _vp]),

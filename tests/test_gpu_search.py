@@ -409,3 +409,32 @@ def test_fp8_overflow_rerun_exact(hn):
     qs = w.queries(db)
     ref, aux, st = _check_search(hn, db, qs, w.k, w.alpha, "fp8", "fp8-rerun", survivor_cap=700)
     assert st["overflow_queries"] > 0
+
+
+@pytest.mark.parametrize("frac", [0.75, 0.5, 0.0])
+def test_soft_beta_mode(hn, frac):
+    """Soft mode (Section 7): beta < alpha replaces alpha in the skip test.
+    The result is a real entry (sim <= the exact best), it is at least as good
+    as every entry the weakened test must keep (dot_K + beta >= L), and the
+    first-pass survivors only shrink as beta falls."""
+    w = hn_inputs.workload(1)
+    db = w.db()
+    qs = w.queries(db)[:64]
+    beta = frac * w.alpha
+    say("soft mode beta=%g" % beta)
+    ix = hn.Index(dev(db), w.k, w.alpha)
+    ei, es, ea = ix.search(dev(qs), aux=True)
+    si, ss, sa = ix.search(dev(qs), beta=beta, aux=True)
+    ei, es, si, ss = (t.cpu().numpy() for t in (ei, es, si, ss))
+    L = sa["seed_sim"].cpu().numpy()
+    assert (ss <= es).all()
+    assert (sa["survivors"].cpu().numpy() <= ea["survivors"].cpu().numpy()).all()
+    for qi in range(len(qs)):
+        assert ss[qi] == oracle.sim(qs[qi], db[si[qi]])
+        must = oracle.survivor_list(db, qs[qi], w.k, beta, L[qi] + 2.0 ** -40)
+        if len(must):
+            best_must = max(oracle.sim(qs[qi], db[j]) for j in must)
+            assert ss[qi] >= best_must
+    recall = float((si == ei).mean())
+    say("recall@1 at beta=%g: %.3f" % (beta, recall))
+    ix.close()
