@@ -40,6 +40,7 @@ PEAK = {  # MI355X published dense peaks
     "fp32_mfma_tflops": 157.3,
     "bf16_mfma_tflops": 2500.0,
     "fp8_mfma_tflops": 5000.0,
+    "int8_mfma_tops": 5000.0,
 }
 
 
@@ -60,7 +61,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=2)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8", "int8"])
     ap.add_argument("--bf-steps", type=int, default=3)
     ap.add_argument("--no-bruteforce", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -293,10 +294,11 @@ def bench_batched(args):
     dom = max((k for k in prof.result if "scan" in k), key=lambda k: prof.result[k]["ms"])
     dom_s = prof.result[dom]["ms"] / 1e3
     peak = PEAK[{"fp32": "fp32_mfma_tflops", "bf16": "bf16_mfma_tflops",
-                 "fp8": "fp8_mfma_tflops"}[args.precision]]
+                 "fp8": "fp8_mfma_tflops", "int8": "int8_mfma_tops"}[args.precision]]
     achieved = flops / dom_s / 1e12
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "TOP/s" if args.precision == "int8" else "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
                 "algorithmic": "sum over databases of 2*Q_d*N_d*K_d = %.4g flop per scan pass, "
                                "all launches of the pass" % flops}
     # the same queries one call per database (eager), and exactness
@@ -338,7 +340,8 @@ def bench_batched(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[args.precision],
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3",
+                  "int8": "int8"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "hn_batched_64db", "databases": len(specs), "entries": N,
                    "queries": Q, "n_range": [min(sp.n for sp in specs), max(sp.n for sp in specs)],
@@ -432,10 +435,11 @@ def main():
     avg_s = kernels[dom]["avg_ms"] / 1e3
     flops = acc.scan_flops(Q, w.n, w.k) / per_step
     peak = PEAK[{"f32": "fp32_mfma_tflops", "bf16": "bf16_mfma_tflops",
-                 "fp8": "fp8_mfma_tflops"}[dom.rsplit("_", 1)[1]]]
+                 "fp8": "fp8_mfma_tflops", "int8": "int8_mfma_tops"}[dom.rsplit("_", 1)[1]]]
     achieved = flops / avg_s / 1e12
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "unit": "TOP/s" if dom.endswith("int8") else "TFLOP/s",
+                "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic(dom, w.name) if per_step == 1 else None,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                 "copy-calibrated)",
@@ -473,7 +477,7 @@ def main():
 
     forms = {}
     if not args.no_forms:
-        for prec in ("fp32", "bf16", "fp8"):
+        for prec in ("fp32", "bf16", "fp8", "int8"):
             if prec == args.precision:
                 forms[prec] = round(qps, 1)
                 continue
@@ -526,7 +530,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[args.precision],
+        "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3",
+                  "int8": "int8"}[args.precision],
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": 128, "k": w.k, "alpha": w.alpha,
                    "queries": Q, "query_mix": "%d perturbed + %d fresh" % (w.n_perturbed, w.n_fresh),

@@ -49,11 +49,13 @@ typedef enum {
  * BF16 scans round-to-nearest-even bfloat16 copies of both operands; FP8
  * scans OCP E4M3FN copies (round to nearest even) of x[:k] / s_x and
  * q[:k] / s_q, with power-of-two scales s_x (one per index, from max |x[:k]|)
- * and s_q (one per query), and is available for k <= 32.  All three
- * accumulate in float32 and keep the search exact: the bound slack covers the
- * rounding (bf16, fp8: by the measured residual norms of the copies), and the
- * low-precision survivors pass a float32 re-check before float64 rescoring. */
-enum { HN_PREC_FP32 = 0, HN_PREC_BF16 = 1, HN_PREC_FP8 = 2 };
+ * and s_q (one per query), and is available for k <= 32.  INT8 (k <= 32)
+ * scans fixed-point codes round(x[:k] / s_x) and round(q[:k] / s_q) in
+ * [-127, 127] with power-of-two scales, summed exactly in int32.  All keep
+ * the search exact: the bound slack covers the rounding (bf16, fp8, int8: by
+ * the measured residual norms of the copies), and the low-precision survivors
+ * pass a float32 re-check before float64 rescoring. */
+enum { HN_PREC_FP32 = 0, HN_PREC_BF16 = 1, HN_PREC_FP8 = 2, HN_PREC_INT8 = 3 };
 
 /* How each query's initial lower bound L_q is found (Algorithm 1 step 2).
  *   PLAIN    two scans: the argmax scan gives the seed b (largest scan score),
@@ -82,9 +84,9 @@ enum {
     HN_BUILD_NO_VALIDATE = 1u << 0, /* skip the block-norm check (bounds stay
                                        rigorous: they use measured norms) */
     HN_BUILD_LOW_PRECISION = 1u << 1 /* accepted, no effect: the BF16 copy and
-                                        (k <= 32) the FP8 copy are always
-                                        built, at 2 and 1 bytes per prefix
-                                        element */
+                                        (k <= 32) the FP8 and INT8 copies are
+                                        always built, at 2, 1 and 1 bytes per
+                                        prefix element */
 };
 
 typedef struct {
@@ -186,9 +188,9 @@ int hn_filter_survivors(const hn_index *ix, const float *queries, int64_t q,
  * Phase 1 of Algorithm 1 with its score buffer: the scan scores
  * s~(q, i) = dot_K(q, x_i) (Eq. 2) as the search kernels compute them, for
  * every query and entry.
- *   precision  HN_PREC_FP32, HN_PREC_BF16 or HN_PREC_FP8 (k <= 32, else
- *              HN_ERR_UNSUPPORTED); FP8 scores are returned rescaled by
- *              s_q s_x (exact: powers of two).
+ *   precision  HN_PREC_FP32, HN_PREC_BF16, HN_PREC_FP8 or HN_PREC_INT8 (the
+ *              last two k <= 32, else HN_ERR_UNSUPPORTED); FP8 and INT8
+ *              scores are returned rescaled by s_q s_x (exact: powers of two).
  *   scores     device, float32 [q][n] row-major.
  */
 int hn_scan_scores(const hn_index *ix, const float *queries, int64_t q, int32_t precision,

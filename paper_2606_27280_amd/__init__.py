@@ -20,7 +20,8 @@ __all__ = ["Index", "bruteforce_top1", "profile", "HNError", "PRECISIONS", "SEED
            "mlp_forward", "mlp_grad", "mlp_adamw", "seed_train", "MultiPlan", "hn_layer",
            "hn_layer_backward"]
 
-PRECISIONS = {"fp32": HN_PREC_FP32, "bf16": HN_PREC_BF16, "fp8": HN_PREC_FP8}
+PRECISIONS = {"fp32": HN_PREC_FP32, "bf16": HN_PREC_BF16, "fp8": HN_PREC_FP8,
+              "int8": _lib.HN_PREC_INT8}
 SEEDS = {"plain": HN_SEED_PLAIN, "learned": HN_SEED_LEARNED, "window": HN_SEED_WINDOW}
 
 

@@ -18,7 +18,7 @@ HN_ERR_OOM = -3
 HN_ERR_DEVICE = -4
 HN_ERR_UNSUPPORTED = -5
 
-HN_PREC_FP32, HN_PREC_BF16, HN_PREC_FP8 = 0, 1, 2
+HN_PREC_FP32, HN_PREC_BF16, HN_PREC_FP8, HN_PREC_INT8 = 0, 1, 2, 3
 HN_SEED_PLAIN, HN_SEED_LEARNED, HN_SEED_WINDOW = 0, 1, 2
 HN_MLP_IN, HN_MLP_H, HN_MLP_OUT, HN_MLP_PARAMS = 128, 256, 512, 230400
 HN_BUILD_NO_VALIDATE = 1 << 0

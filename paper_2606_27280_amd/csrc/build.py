@@ -9,7 +9,8 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 SOURCES = ["hn_index.hip", "hn_search.hip", "hn_profile.hip", "hn_scan_f32n.hip",
            "hn_scan_f32w.hip", "hn_scan_bf16.hip", "hn_scan_fp8.hip", "hn_seed.hip",
-           "hn_scan_multi.hip", "hn_multi.hip", "hn_layer.hip"]
+           "hn_scan_multi.hip", "hn_multi.hip", "hn_layer.hip",
+           "hn_scan_i8.hip"]
 OUT = os.path.join(PKG, "libhnsearch.so")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

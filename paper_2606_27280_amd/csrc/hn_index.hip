@@ -80,6 +80,7 @@ struct BuildStats {
     unsigned long long key_major16, key_res16;          // bf16 copy
     unsigned long long key_amax;                        // max |x[:k]| (float bits)
     unsigned long long key_major8, key_res8;            // fp8 copy
+    unsigned long long key_majori, key_resi;            // int8 copy
     unsigned long long bad_rows, nonfinite_rows;
     long long first_bad;
 };
@@ -89,6 +90,7 @@ __global__ void build_stats_init(BuildStats *s) {
         s->key_major = s->key_minor = s->key_full = 0;
         s->key_major16 = s->key_res16 = 0;
         s->key_amax = s->key_major8 = s->key_res8 = 0;
+        s->key_majori = s->key_resi = 0;
         s->bad_rows = s->nonfinite_rows = 0;
         s->first_bad = 0x7fffffffffffffffll;
     }
@@ -192,19 +194,21 @@ __global__ __launch_bounds__(256) void build_major16(const float *__restrict__ d
     out[t] = (uint16_t)(__float_as_uint(bf16_round(v)) >> 16);
 }
 
-// fp8 copy: thread per row; the scale comes from the measured max |x[:k]|
-// (every thread derives the same power of two), and the row's residual
-// ||scale * fp8(x / scale) - x|| and scaled-copy norm feed the bound slack.
+// fp8 and int8 copies: thread per row; each scale comes from the measured
+// max |x[:k]| (every thread derives the same power of two), and the row's
+// residual ||scale * code - x|| and scaled-copy norm feed the bound slack.
 __global__ __launch_bounds__(256) void build_major8(const float *__restrict__ db, int64_t n,
                                                     int64_t n_pad, int k, int k8,
-                                                    BuildStats *st, uint8_t *__restrict__ out) {
+                                                    BuildStats *st, uint8_t *__restrict__ out,
+                                                    int8_t *__restrict__ out_i8) {
     __shared__ double sh[4];
-    const float scale = fp8_scale_for((float)sim_of_key(st->key_amax));
-    const float inv = 1.0f / scale;  // exact: a power of two
+    const float amax = (float)sim_of_key(st->key_amax);
+    const float scale = fp8_scale_for(amax), scale_i = int8_scale_for(amax);
+    const float inv = 1.0f / scale, inv_i = 1.0f / scale_i;  // exact: powers of two
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double rn = 0, rr = 0;
+    double rn = 0, rr = 0, rni = 0, rri = 0;
     if (i < n_pad) {
-        double sn = 0, sr = 0;
+        double sn = 0, sr = 0, sni = 0, sri = 0;
         for (int c = 0; c < k8; ++c) {
             const float v = (i < n && c < k) ? db[i * kDim + c] : 0.0f;
             const uint8_t code = fp8_e4m3(v * inv);
@@ -212,17 +216,28 @@ __global__ __launch_bounds__(256) void build_major8(const float *__restrict__ db
             const double back = (double)fp8_e4m3_value(code) * (double)scale;
             sn = fma(back, back, sn);
             sr = fma(back - (double)v, back - (double)v, sr);
+            const int8_t ci = int8_code(v * inv_i);
+            out_i8[i * k8 + c] = ci;
+            const double bi = (double)ci * (double)scale_i;
+            sni = fma(bi, bi, sni);
+            sri = fma(bi - (double)v, bi - (double)v, sri);
         }
         if (i < n) {
             rn = sqrt(sn);
             rr = sqrt(sr);
+            rni = sqrt(sni);
+            rri = sqrt(sri);
         }
     }
     const double a = block_max<256>(rn, sh);
     const double b = block_max<256>(rr, sh);
+    const double c = block_max<256>(rni, sh);
+    const double d = block_max<256>(rri, sh);
     if (threadIdx.x == 0) {
         atomicMax(&st->key_major8, key_of(a));
         atomicMax(&st->key_res8, key_of(b));
+        atomicMax(&st->key_majori, key_of(c));
+        atomicMax(&st->key_resi, key_of(d));
     }
 }
 
@@ -245,6 +260,7 @@ void free_index(hn_index *ix) {
     if (ix->major32) (void)hipFree(ix->major32);
     if (ix->major16) (void)hipFree(ix->major16);
     if (ix->major8) (void)hipFree(ix->major8);
+    if (ix->major_i8) (void)hipFree(ix->major_i8);
     if (ix->seed_w) (void)hipFree(ix->seed_w);
     if (ix->seed_b) (void)hipFree(ix->seed_b);
     if (ix->seed_anchor) (void)hipFree(ix->seed_anchor);
@@ -319,7 +335,8 @@ extern "C" int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, 
         hipMalloc(&ix->rows, (size_t)n * kDim * sizeof(float)) != hipSuccess ||
         hipMalloc(&ix->major32, (size_t)ix->n_pad * ix->kp * sizeof(float)) != hipSuccess ||
         hipMalloc(&ix->major16, (size_t)ix->n_pad * ix->kb * sizeof(uint16_t)) != hipSuccess ||
-        (ix->k8 && hipMalloc(&ix->major8, (size_t)ix->n_pad * ix->k8) != hipSuccess)) {
+        (ix->k8 && hipMalloc(&ix->major8, (size_t)ix->n_pad * ix->k8) != hipSuccess) ||
+        (ix->k8 && hipMalloc(&ix->major_i8, (size_t)ix->n_pad * ix->k8) != hipSuccess)) {
         (void)hipGetLastError();
         fail(HN_ERR_OOM, "device allocation failed for n=%lld", (long long)n);
         return cleanup(HN_ERR_OOM);
@@ -332,7 +349,7 @@ extern "C" int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, 
                        db, n, ix->n_pad, k, ix->kb, ix->major16);
     if (ix->k8)
         hipLaunchKernelGGL(build_major8, dim3(grid_for(ix->n_pad, 256)), dim3(256), 0, s, db, n,
-                           ix->n_pad, k, ix->k8, st, ix->major8);
+                           ix->n_pad, k, ix->k8, st, ix->major8, ix->major_i8);
     hipError_t e = hipMemcpyAsync(ix->rows, db, (size_t)n * kDim * sizeof(float),
                                   hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess) e = hipGetLastError();
@@ -362,9 +379,12 @@ extern "C" int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, 
         const float amax = (float)key_to_double_host(h.key_amax);
         (void)frexpf(amax, &ex);
         ix->scale8 = amax > 0.0f ? ldexpf(1.0f, ex - 8) : 1.0f;
+        ix->scale_i8 = amax > 0.0f ? ldexpf(1.0f, ex - 7) : 1.0f;
     }
     ix->mu_major8 = round_up_norm(key_to_double_host(h.key_major8));
     ix->res8 = round_up_norm(key_to_double_host(h.key_res8));
+    ix->mu_major_i8 = round_up_norm(key_to_double_host(h.key_majori));
+    ix->res_i8 = round_up_norm(key_to_double_host(h.key_resi));
     (void)hipFree(st);
     *out = ix;
     return HN_OK;

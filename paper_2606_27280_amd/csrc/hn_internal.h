@@ -131,6 +131,19 @@ __host__ __device__ __forceinline__ float fp8_scale_for(float amax) {
     return ldexpf(1.0f, e - 8);
 }
 
+// Power-of-two scale for int8 codes: 2^(e - 7) with amax = f 2^e,
+// 0.5 <= f < 1, so |x| / scale < 128; codes are rounded to nearest even and
+// clamped to [-127, 127] (the measured residuals cover the clamp).
+__host__ __device__ __forceinline__ float int8_scale_for(float amax) {
+    if (!(amax > 0.0f)) return 1.0f;
+    int e;
+    (void)frexpf(amax, &e);
+    return ldexpf(1.0f, e - 7);
+}
+__device__ __forceinline__ int8_t int8_code(float scaled) {
+    return (int8_t)fminf(127.0f, fmaxf(-127.0f, rintf(scaled)));
+}
+
 // Higham's gamma_n(u).
 __host__ __device__ __forceinline__ double gamma_n(int n, double u) {
     return (double)n * u / (1.0 - (double)n * u);
@@ -162,6 +175,10 @@ struct hn_index {
     float scale8 = 1.0f;         // power-of-two scale of the fp8 copy
     double mu_major8 = 0;        // max ||scale8 * fp8(x[:k])||, rounded up
     double res8 = 0;             // max ||scale8 * fp8(x[:k]) - x[:k]||, rounded up
+    int8_t *major_i8 = nullptr;  // [n_pad][k8] int8 codes of x[:k] / scale_i8 (k <= 32)
+    float scale_i8 = 1.0f;       // power-of-two scale of the int8 copy
+    double mu_major_i8 = 0;      // max ||scale_i8 * code||, rounded up
+    double res_i8 = 0;           // max ||scale_i8 * code - x[:k]||, rounded up
     // learned seed model (hn_set_seed_model): bf16 weights W1 | W2 | W3,
     // float32 biases b1 | b2 | b3, anchor entry ids
     uint16_t *seed_w = nullptr;

@@ -1,14 +1,17 @@
 // The HN layer (Eq. 1) and its vector-Jacobian product: the step that puts
-// embeddings on the split sphere before they enter an index.  One wave per
-// 128-d row, two elements per lane (one 512 B row per wave), block norms in
-// float64, every output rounded once to float32.  HBM-bound: 1 KiB moved
-// per row forward, 1.5 KiB backward.
+// embeddings on the split sphere before they enter an index.  A wave takes
+// kRows consecutive 128-d rows, two elements per lane: all of its row loads
+// are issued before any arithmetic, so each wave keeps kRows x 512 B in
+// flight.  Block norms in float64, every output rounded once to float32.
+// HBM-bound: 1 KiB moved per row forward, 1.5 KiB backward.
 #include <math.h>
 
 #include "hn_internal.h"
 
 namespace hn {
 namespace {
+
+constexpr int kRows = 8;  // rows per wave
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -17,14 +20,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Row status: 0 ok; 1 zero major block; 2 zero minor block with alpha > 0;
 // 3 a non-finite component.  Blocks that cannot be normalised come out zero.
-__global__ __launch_bounds__(256) void layer_fwd(const float2 *__restrict__ f, int64_t b, int k,
-                                                 double c_major, double c_minor,
-                                                 float2 *__restrict__ out,
-                                                 int32_t *__restrict__ status) {
-    const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= b) return;
-    const float2 v = f[r * 64 + lane];
+__device__ __forceinline__ void fwd_row(const float2 v, const int64_t r, const int lane, int k,
+                                        double c_major, double c_minor,
+                                        float2 *__restrict__ out, int32_t *__restrict__ status) {
     const int j0 = 2 * lane, j1 = j0 + 1;
     const double a0 = v.x, a1 = v.y;
     const double sM = wave_sum((j0 < k ? a0 * a0 : 0.0) + (j1 < k ? a1 * a1 : 0.0));
@@ -41,15 +39,26 @@ __global__ __launch_bounds__(256) void layer_fwd(const float2 *__restrict__ f, i
     if (status && lane == 0) status[r] = !finite ? 3 : (!okM ? 1 : (!okm ? 2 : 0));
 }
 
-// dL/df for y = c u / ||u|| per block: (c / ||u||) (g - v (v . g)), v = u / ||u||.
-__global__ __launch_bounds__(256) void layer_bwd(const float2 *__restrict__ f,
-                                                 const float2 *__restrict__ g, int64_t b, int k,
+__global__ __launch_bounds__(256) void layer_fwd(const float2 *__restrict__ f, int64_t b, int k,
                                                  double c_major, double c_minor,
-                                                 float2 *__restrict__ grad) {
+                                                 float2 *__restrict__ out,
+                                                 int32_t *__restrict__ status) {
     const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= b) return;
-    const float2 v = f[r * 64 + lane], w = g[r * 64 + lane];
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kRows;
+    if (r0 >= b) return;
+    float2 v[kRows];
+#pragma unroll
+    for (int t = 0; t < kRows; ++t)
+        v[t] = r0 + t < b ? f[(r0 + t) * 64 + lane] : make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int t = 0; t < kRows; ++t)
+        if (r0 + t < b) fwd_row(v[t], r0 + t, lane, k, c_major, c_minor, out, status);
+}
+
+// dL/df for y = c u / ||u|| per block: (c / ||u||) (g - v (v . g)), v = u / ||u||.
+__device__ __forceinline__ void bwd_row(const float2 v, const float2 w, const int64_t r,
+                                        const int lane, int k, double c_major, double c_minor,
+                                        float2 *__restrict__ grad) {
     const int j0 = 2 * lane, j1 = j0 + 1;
     const double a0 = v.x, a1 = v.y, g0 = w.x, g1 = w.y;
     const bool M0 = j0 < k, M1 = j1 < k;
@@ -66,7 +75,26 @@ __global__ __launch_bounds__(256) void layer_bwd(const float2 *__restrict__ f,
     grad[r * 64 + lane] = make_float2(d(a0, g0, M0), d(a1, g1, M1));
 }
 
-unsigned blocks_of_rows(int64_t b) { return (unsigned)((b + 3) / 4); }
+__global__ __launch_bounds__(256) void layer_bwd(const float2 *__restrict__ f,
+                                                 const float2 *__restrict__ g, int64_t b, int k,
+                                                 double c_major, double c_minor,
+                                                 float2 *__restrict__ grad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kRows;
+    if (r0 >= b) return;
+    float2 v[kRows], w[kRows];
+#pragma unroll
+    for (int t = 0; t < kRows; ++t) {
+        const bool in = r0 + t < b;
+        v[t] = in ? f[(r0 + t) * 64 + lane] : make_float2(0.0f, 0.0f);
+        w[t] = in ? g[(r0 + t) * 64 + lane] : make_float2(0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int t = 0; t < kRows; ++t)
+        if (r0 + t < b) bwd_row(v[t], w[t], r0 + t, lane, k, c_major, c_minor, grad);
+}
+
+unsigned blocks_of_rows(int64_t b) { return (unsigned)((b + 4 * kRows - 1) / (4 * kRows)); }
 
 int check_layer(int64_t b, int32_t d, int32_t k, double alpha) {
     if (d != kDim) return fail(HN_ERR_INVALID_ARG, "d must be 128 (got %d)", d);

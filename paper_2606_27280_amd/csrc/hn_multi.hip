@@ -381,9 +381,7 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
         void *opd = op + op_off[d] * esz;
         ScanArgs A;
         memset(&A, 0, sizeof A);
-        A.x = o.precision == HN_PREC_FP32   ? (const void *)ix->major32
-              : o.precision == HN_PREC_BF16 ? (const void *)ix->major16
-                                            : (const void *)ix->major8;
+        A.x = stream_of(ix, o.precision);
         A.x_stride = w;
         A.qs = opd;
         A.q_stride = w;
@@ -453,8 +451,11 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
         } else if (o.precision == HN_PREC_BF16) {
             Q.op16 = static_cast<uint16_t *>(opd);
             Q.w16 = w;
-        } else {
+        } else if (o.precision == HN_PREC_FP8) {
             Q.op8 = static_cast<uint8_t *>(opd);
+            Q.w8 = w;
+        } else {
+            Q.opi = static_cast<int8_t *>(opd);
             Q.w8 = w;
         }
         Q.qn = P->qn + pad_base[d];

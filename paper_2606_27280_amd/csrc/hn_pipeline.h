@@ -29,7 +29,9 @@ struct QNorm {
     double major, minor, full;  // rounded-up float64 block norms
     double res16;               // ||bf16(q[:k]) - q[:k]||, rounded up
     double res8;                // ||s8 fp8(q[:k] / s8) - q[:k]||, rounded up
+    double resi;                // ||si code - q[:k]|| of the int8 operand, rounded up
     float sc8;                  // s8: power-of-two scale of the fp8 operand
+    float sci;                  // si: power-of-two scale of the int8 operand
     int bad;                    // non-finite component
 };
 
@@ -48,6 +50,7 @@ struct PrepArgs {
     float *op32;
     uint16_t *op16;
     uint8_t *op8;
+    int8_t *opi;  // int8 codes, width w8
     QNorm *qn;
     unsigned *work;
 };
@@ -62,6 +65,8 @@ __device__ __forceinline__ void prep_one(const PrepArgs &P, const int64_t i) {
             for (int c = 0; c < P.w16; ++c) P.op16[i * P.w16 + c] = 0;
         if (P.op8)
             for (int c = 0; c < P.w8; ++c) P.op8[i * P.w8 + c] = 0;
+        if (P.opi)
+            for (int c = 0; c < P.w8; ++c) P.opi[i * P.w8 + c] = 0;
         return;
     }
     const int k = P.k;
@@ -90,6 +95,8 @@ __device__ __forceinline__ void prep_one(const PrepArgs &P, const int64_t i) {
     r.res16 = sqrt(sr) * up;
     r.res8 = 0.0;
     r.sc8 = 1.0f;
+    r.resi = 0.0;
+    r.sci = 1.0f;
     r.bad = finite ? 0 : 1;
     if (P.op32)
         for (int c = 0; c < P.w32; ++c) P.op32[i * P.w32 + c] = (c < k && finite) ? v[c] : 0.0f;
@@ -110,6 +117,20 @@ __device__ __forceinline__ void prep_one(const PrepArgs &P, const int64_t i) {
         }
         r.res8 = sqrt(s8) * up;
         r.sc8 = sc;
+    }
+    if (P.opi) {
+        const float sc = finite ? int8_scale_for(amax) : 1.0f;
+        const float inv = 1.0f / sc;  // exact: a power of two
+        double si = 0;
+        for (int c = 0; c < P.w8; ++c) {
+            const float f = (c < k && finite) ? v[c] : 0.0f;
+            const int8_t code = int8_code(f * inv);
+            P.opi[i * P.w8 + c] = code;
+            const double e = (double)code * (double)sc - (double)f;
+            si = fma(e, e, si);
+        }
+        r.resi = sqrt(si) * up;
+        r.sci = sc;
     }
     P.qn[i] = r;
 }
@@ -141,9 +162,10 @@ struct SeedArgs {
     // or the smaller of the two; plus abs
     double scan_rel, scan_mu, scan_abs;
     int scan_res;  // 0: worst case; 1: min(worst case, residual); 2: residual
-    int fp8;       // residuals of the fp8 operands; thresholds in scan units
+    int scaled;    // 1: fp8, 2: int8 operands (residuals of the scaled copies,
+                   // thresholds in scan units s_q s_x); 0: neither
     double res_mu, res_x, res_acc_rel;
-    double scale_x;  // fp8: power-of-two scale of the entry copy
+    double scale_x;  // scaled copies: power-of-two scale of the entry copy
     const double *lower;  // given L (filter-only, learned or no seed); NULL: plain seed
     const int64_t *lower_idx;  // entry of each given L, or NULL (none)
     // single-pass window (NULL: none): exact width 2 (beta + eps_q) in scan
@@ -254,7 +276,7 @@ __device__ __forceinline__ void seed_one(const SeedArgs &S, const int64_t i, con
     // slack: scan rounding + stored-norm excess (Eq. 3) + float64 evaluation
     double es = S.scan_rel * qn.major * S.scan_mu;
     if (S.scan_res) {
-        const double rq = S.fp8 ? qn.res8 : qn.res16;
+        const double rq = S.scaled == 1 ? qn.res8 : (S.scaled == 2 ? qn.resi : qn.res16);
         const double er =
             rq * S.res_mu + qn.major * S.res_x + S.res_acc_rel * (qn.major + rq) * S.res_mu;
         es = S.scan_res == 2 ? er : fmin(es, er);
@@ -263,13 +285,16 @@ __device__ __forceinline__ void seed_one(const SeedArgs &S, const int64_t i, con
     double en = fmax(0.0, qn.minor * S.mu_minor - S.alpha);
     double e64 = gamma_n(kDim, kU64) * qn.full * S.mu_full;
     double eps = (es + en + e64) * (1.0 + ldexp(1.0, -30)) + ldexp(1.0, -40);
-    // fp8 scans score q~ . x~ with q = s_q q~ and x = s_x x~ (powers of two):
-    // the threshold in scan units is the same bound divided by s_q s_x, exact
-    const double unit = S.fp8 ? 1.0 / ((double)qn.sc8 * S.scale_x) : 1.0;
+    // fp8 and int8 scans score q~ . x~ with q = s_q q~ and x = s_x x~ (powers
+    // of two): the threshold in scan units is the bound divided by s_q s_x
+    const double unit =
+        S.scaled ? 1.0 / ((double)(S.scaled == 1 ? qn.sc8 : qn.sci) * S.scale_x) : 1.0;
     S.thr[i] = round_down_f32((L - S.beta - eps) * unit);
     if (S.win_scan) {
         // |s~| <= (||q_M|| + r_q) max ||x^_M|| (1 + 2^-20), in scan units
-        const double rq = S.fp8 ? qn.res8 : (S.scan_res ? qn.res16 : 0.0);
+        const double rq = S.scaled == 1   ? qn.res8
+                          : S.scaled == 2 ? qn.resi
+                                          : (S.scan_res ? qn.res16 : 0.0);
         const double bound = (qn.major + rq) * S.bound_mu * unit * (1.0 + ldexp(1.0, -20));
         const double w = 2.0 * (S.beta + eps) * unit;
         S.win[i] = w;
@@ -302,13 +327,16 @@ int stream_width(const hn_index *ix, int precision) {
 const void *stream_of(const hn_index *ix, int precision) {
     return precision == HN_PREC_FP32   ? (const void *)ix->major32
            : precision == HN_PREC_BF16 ? (const void *)ix->major16
-                                       : (const void *)ix->major8;
+           : precision == HN_PREC_FP8  ? (const void *)ix->major8
+                                       : (const void *)ix->major_i8;
 }
 int check_precision(const hn_index *ix, int precision) {
-    if (precision != HN_PREC_FP32 && precision != HN_PREC_BF16 && precision != HN_PREC_FP8)
+    if (precision != HN_PREC_FP32 && precision != HN_PREC_BF16 && precision != HN_PREC_FP8 &&
+        precision != HN_PREC_INT8)
         return fail(HN_ERR_UNSUPPORTED, "precision %d is not available", precision);
-    if (precision == HN_PREC_FP8 && ix->k8 == 0)
-        return fail(HN_ERR_UNSUPPORTED, "the fp8 scan needs k <= 32 (k = %d)", ix->k);
+    if ((precision == HN_PREC_FP8 || precision == HN_PREC_INT8) && ix->k8 == 0)
+        return fail(HN_ERR_UNSUPPORTED, "the %s scan needs k <= 32 (k = %d)",
+                    precision == HN_PREC_FP8 ? "fp8" : "int8", ix->k);
     return HN_OK;
 }
 
@@ -340,7 +368,7 @@ inline void scan_slack(const hn_index *ix, int precision, SeedArgs &S) {
         S.res_mu = ix->mu_major16;
         S.res_x = ix->res16;
         S.res_acc_rel = gamma_n(ix->k, kU32);
-    } else {
+    } else if (precision == HN_PREC_FP8) {
         // fp8: the residual form only (subnormal codes have no relative
         // bound); the products are summed by the bf16 matrix core (the codes
         // are decoded exactly to bf16), float32 accumulation.
@@ -348,11 +376,24 @@ inline void scan_slack(const hn_index *ix, int precision, SeedArgs &S) {
         S.scan_mu = 0.0;
         S.scan_abs = ix->k * ldexp(1.0, -125);
         S.scan_res = 2;
-        S.fp8 = 1;
+        S.scaled = 1;
         S.scale_x = ix->scale8;
         S.res_mu = ix->mu_major8;
         S.res_x = ix->res8;
         S.res_acc_rel = gamma_n(ix->k, kU32);
+    } else {
+        // int8: the residual form; the matrix core sums integer products
+        // exactly in int32 (|sum| <= 32 * 127^2 < 2^24, so the conversion to
+        // float32 is exact too): no accumulation term.
+        S.scan_rel = 0.0;
+        S.scan_mu = 0.0;
+        S.scan_abs = 0.0;
+        S.scan_res = 2;
+        S.scaled = 2;
+        S.scale_x = ix->scale_i8;
+        S.res_mu = ix->mu_major_i8;
+        S.res_x = ix->res_i8;
+        S.res_acc_rel = 0.0;
     }
 }
 
@@ -679,12 +720,15 @@ unsigned blocks_for(int64_t items, int per = 256) {
 
 // precision 0: float32 stream of width w; 1: bf16 stream of width w.
 const char *scan_tag(int mode, int precision) {
-    static const char *const tags[4][3] = {
-        {"scan_argmax_f32", "scan_argmax_bf16", "scan_argmax_fp8"},
-        {"scan_filter_f32", "scan_filter_bf16", "scan_filter_fp8"},
-        {"scan_window_f32", "scan_window_bf16", "scan_window_fp8"},
-        {"scan_store_f32", "scan_store_bf16", "scan_store_fp8"}};
-    return tags[mode][precision == HN_PREC_FP32 ? 0 : (precision == HN_PREC_BF16 ? 1 : 2)];
+    static const char *const tags[4][4] = {
+        {"scan_argmax_f32", "scan_argmax_bf16", "scan_argmax_fp8", "scan_argmax_int8"},
+        {"scan_filter_f32", "scan_filter_bf16", "scan_filter_fp8", "scan_filter_int8"},
+        {"scan_window_f32", "scan_window_bf16", "scan_window_fp8", "scan_window_int8"},
+        {"scan_store_f32", "scan_store_bf16", "scan_store_fp8", "scan_store_int8"}};
+    return tags[mode][precision == HN_PREC_FP32   ? 0
+                      : precision == HN_PREC_BF16 ? 1
+                      : precision == HN_PREC_FP8  ? 2
+                                                  : 3];
 }
 
 template <int MODE>
@@ -699,6 +743,8 @@ int launch_scan(int precision, int w, int cfg, const Plan &p, const ScanArgs &A,
         rc = launch_scan_bf16(MODE, w, cfg, p, A, s);
     else if (precision == HN_PREC_FP8)
         rc = launch_scan_fp8(MODE, w, cfg, p, A, s);
+    else if (precision == HN_PREC_INT8)
+        rc = launch_scan_int8(MODE, w, cfg, p, A, s);
     else
         return fail(HN_ERR_UNSUPPORTED, "precision %d is not available", precision);
     if (rc) return fail(HN_ERR_INVALID_ARG, "no scan kernel for mode %d width %d config %d", MODE, w, cfg);

@@ -250,6 +250,32 @@ struct FP8Tile32 : Shape32 {
     }
 };
 
+// INT8 fixed-point stream of width W on 32x32x16 MFMA (2 lane groups, W/2
+// codes each, in steps of 8), summed exactly in int32; the sums are converted
+// to float32 for the shared epilogue (exact: |sum| < 2^24).
+typedef int v16i __attribute__((ext_vector_type(16)));
+template <int W>
+struct I8Tile32 : Shape32 {
+    typedef int8_t Elem;
+    static constexpr int kSlice = W / 2;
+    static constexpr int kFragRegs = kSlice / 4;
+    typedef Regs<kFragRegs> Frag;
+    HN_SAME_Q_OPERAND
+    __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
+        v16i acc = {};
+#pragma unroll
+        for (int c = 0; c < kSlice / 8; ++c) {
+            const long a = (long)((unsigned long)x.v[2 * c] | ((unsigned long)x.v[2 * c + 1] << 32));
+            const long b = (long)((unsigned long)q.v[2 * c] | ((unsigned long)q.v[2 * c + 1] << 32));
+            acc = __builtin_amdgcn_mfma_i32_32x32x16_i8(a, b, acc, 0, 0, 0);
+        }
+        Acc out;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) out[v] = (float)acc[v];
+        return out;
+    }
+};
+
 // Registers one tile of a configuration holds per lane (scores + query
 // operand); a configuration is compiled when NQ times this stays within budget.
 template <class Tile>
@@ -277,7 +303,7 @@ __device__ __forceinline__ float acc_max(const Acc &a) {
 // global list with one atomic per wave at the end of the work item.  A wave
 // whose buffer fills marks the item for a re-run by scan_redo_kernel, which
 // flushes whenever its buffer fills (Direct); the set of pairs is the same.
-constexpr int kEmitCap = 512;  // pairs per wave buffer (>= 64 lanes x 4 slots)
+constexpr int kEmitCap = 1024;  // pairs per wave buffer (>= 64 lanes x 4 slots)
 
 struct EmitBuf {
     int2 *pairs;  // LDS [kEmitCap]
@@ -748,7 +774,8 @@ inline void launch_one(const Plan &p, const ScanArgs &A, hipStream_t s) {
                            dim3(persistent_grid<Tile, kCfgNQ[C], kCfgWQ[C], MODE>(p.n_items)),
                            dim3(256), 0, s, A);
         if constexpr (MODE == kFilter || MODE == kWindow)
-            hipLaunchKernelGGL((scan_redo_kernel<Tile, kCfgNQ[C], kCfgWQ[C], MODE>), dim3(256),
+            hipLaunchKernelGGL((scan_redo_kernel<Tile, kCfgNQ[C], kCfgWQ[C], MODE>),
+                               dim3(persistent_grid<Tile, kCfgNQ[C], kCfgWQ[C], MODE>(p.n_items)),
                                dim3(256), 0, s, A);
     }
 }
@@ -800,7 +827,8 @@ inline void launch_multi_one(const ScanArgs *dbs, const int2 *items, int n_items
                            dim3(256), 0, s, dbs, items, n_items);
         if constexpr (MODE == kFilter)
             hipLaunchKernelGGL((scan_multi_redo_kernel<Tile, kCfgNQ[C], kCfgWQ[C], MODE>),
-                               dim3(256), dim3(256), 0, s, dbs, items, redo, redo_count);
+                               dim3(persistent_grid<Tile, kCfgNQ[C], kCfgWQ[C], MODE>(n_items)),
+                               dim3(256), 0, s, dbs, items, redo, redo_count);
     }
 }
 
@@ -836,6 +864,7 @@ struct TileInfo {
 };
 inline TileInfo tile_info(int precision, int w) {
     if (precision == HN_PREC_FP8) return TileInfo{32, 32, 16 + w / 4, 2};
+    if (precision == HN_PREC_INT8) return TileInfo{32, 32, 16 + w / 8, 2};
     if (precision == HN_PREC_FP32) {
         if (w <= 32) return TileInfo{32, 32, 16 + w / 2, 2};
         return TileInfo{16, 16, 4 + w / 4, 4};
@@ -853,6 +882,8 @@ int launch_scan_bf16(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
                      hipStream_t s);        // widths 16, 32 (32x32), 64, 128 (16x16)
 int launch_scan_fp8(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
                     hipStream_t s);         // widths 16, 32 (32x32)
+int launch_scan_int8(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
+                     hipStream_t s);        // widths 16, 32 (32x32)
 // Several databases of one stream width in one launch: float32 widths 8, 16,
 // 32; bf16 and fp8 widths 16, 32.  Nonzero if not compiled.
 int launch_scan_multi(int precision, int mode, int w, int cfg, const ScanArgs *dbs,

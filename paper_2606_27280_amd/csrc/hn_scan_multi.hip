@@ -23,6 +23,11 @@ int launch_scan_multi(int precision, int mode, int w, int cfg, const ScanArgs *d
             case 16: return HN_MULTI(FP8Tile32<16>);
             case 32: return HN_MULTI(FP8Tile32<32>);
         }
+    } else if (precision == HN_PREC_INT8) {
+        switch (w) {
+            case 16: return HN_MULTI(I8Tile32<16>);
+            case 32: return HN_MULTI(I8Tile32<32>);
+        }
     }
 #undef HN_MULTI
     return 1;

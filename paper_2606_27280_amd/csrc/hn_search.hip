@@ -24,6 +24,7 @@ struct Work {
     float *op32 = nullptr;
     uint16_t *op16 = nullptr;
     uint8_t *op8 = nullptr;
+    int8_t *opi = nullptr;
     QNorm *qn = nullptr;
     float *part_val = nullptr;
     int32_t *part_idx = nullptr;
@@ -47,7 +48,8 @@ struct Work {
 const void *operands_of(const Work &W) {
     return W.precision == HN_PREC_FP32   ? (const void *)W.op32
            : W.precision == HN_PREC_BF16 ? (const void *)W.op16
-                                         : (const void *)W.op8;
+           : W.precision == HN_PREC_FP8  ? (const void *)W.op8
+                                         : (const void *)W.opi;
 }
 
 void launch_prep(const hn_index *ix, const float *queries, int64_t q, int64_t q_pad, Work &W,
@@ -63,6 +65,7 @@ void launch_prep(const hn_index *ix, const float *queries, int64_t q, int64_t q_
     P.op32 = W.op32;
     P.op16 = W.op16;
     P.op8 = W.op8;
+    P.opi = W.opi;
     P.qn = W.qn;
     P.work = W.work;
     ProfScope prof_(s, "prep_queries");
@@ -156,7 +159,9 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     if (rc) return rc;
     W.op32 = ar->take<float>(qp * ix->kp);
     W.op16 = ar->take<uint16_t>(qp * ix->kb);
-    W.op8 = ix->k8 ? ar->take<uint8_t>(qp * ix->k8) : nullptr;
+    W.op32 = W.precision == HN_PREC_FP32 ? W.op32 : nullptr;
+    W.op8 = W.precision == HN_PREC_FP8 ? ar->take<uint8_t>(qp * ix->k8) : nullptr;
+    W.opi = W.precision == HN_PREC_INT8 ? ar->take<int8_t>(qp * ix->k8) : nullptr;
     W.qn = ar->take<QNorm>(qp);
     W.part_val = ar->take<float>(part);
     W.part_idx = ar->take<int32_t>(part);
@@ -250,7 +255,8 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
         S.init_best = W.init_best;
         S.bound_mu = W.precision == HN_PREC_FP32   ? ix->mu_major
                      : W.precision == HN_PREC_BF16 ? ix->mu_major16
-                                                   : ix->mu_major8;
+                     : W.precision == HN_PREC_FP8  ? ix->mu_major8
+                                                   : ix->mu_major_i8;
     }
     S.qn = W.qn;
     S.thr = W.thr;
@@ -298,11 +304,11 @@ ScanArgs filter_args(const hn_index *ix, const Work &W, int64_t q, int2 *pairs, 
 }
 
 __global__ __launch_bounds__(256) void scale_scores(float *scores, int64_t q, int64_t n,
-                                                   const QNorm *qn, float scale_x) {
+                                                   const QNorm *qn, float scale_x, int int8) {
     const int64_t total = q * n;
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * 256)
-        scores[t] *= qn[t / n].sc8 * scale_x;
+        scores[t] *= (int8 ? qn[t / n].sci : qn[t / n].sc8) * scale_x;
 }
 
 
@@ -570,7 +576,8 @@ extern "C" int hn_search_top1(const hn_index *ix, const float *queries, int64_t 
             a2.slack = aux->slack ? aux->slack + q0 : nullptr;
         }
         hn_search_stats st{0, 0};
-        if (o.seed == HN_SEED_PLAIN && o.precision != HN_PREC_FP8)
+        if (o.seed == HN_SEED_PLAIN && o.precision != HN_PREC_FP8 &&
+            o.precision != HN_PREC_INT8)
             rc = search_batch(ix, queries + q0 * kDim, nb, out_idx + q0, out_sim + q0, o,
                               aux ? &a2 : nullptr, stats ? &st : nullptr, s);
         else
@@ -645,7 +652,8 @@ extern "C" int hn_scan_scores(const hn_index *ix, const float *queries, int64_t 
     if (rc) return rc;
     W.op32 = ar->take<float>(p.q_pad * ix->kp);
     W.op16 = ar->take<uint16_t>(p.q_pad * ix->kb);
-    W.op8 = ix->k8 ? ar->take<uint8_t>(p.q_pad * ix->k8) : nullptr;
+    W.op8 = precision == HN_PREC_FP8 ? ar->take<uint8_t>(p.q_pad * ix->k8) : nullptr;
+    W.opi = precision == HN_PREC_INT8 ? ar->take<int8_t>(p.q_pad * ix->k8) : nullptr;
     W.qn = ar->take<QNorm>(p.q_pad);
     W.work = ar->take<unsigned>(kWorkWords);
     W.redo = ar->take<int>(p.n_items);
@@ -668,10 +676,11 @@ extern "C" int hn_scan_scores(const hn_index *ix, const float *queries, int64_t 
     A.redo = W.redo;
     A.redo_count = W.work + 2 * kXcds;
     rc = launch_scan<kStore>(precision, W.width, W.cfg, p, A, s);
-    if (rc || precision != HN_PREC_FP8) return rc;
-    // fp8 scores come out in units of s_q s_x: rescale (exact, powers of two)
+    if (rc || (precision != HN_PREC_FP8 && precision != HN_PREC_INT8)) return rc;
+    // fp8 / int8 scores come out in units of s_q s_x: rescale (exact, powers of two)
     hipLaunchKernelGGL(scale_scores, dim3(2048), dim3(256), 0, s, scores, q, ix->n, W.qn,
-                       ix->scale8);
+                       precision == HN_PREC_FP8 ? ix->scale8 : ix->scale_i8,
+                       precision == HN_PREC_INT8 ? 1 : 0);
     HN_HIP(hipGetLastError());
     return HN_OK;
 }

@@ -68,7 +68,7 @@ def _check(idx, sim, ref, what):
     assert (np.abs(sim - rs) <= SIM_TOL).all(), what
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8", "int8"])
 def test_multi_matches_oracle(hn, precision):
     dbs = _dbs(7000)
     ref = _reference(dbs)

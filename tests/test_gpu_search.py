@@ -137,6 +137,43 @@ def test_scan_scores_fp8_exact_products_and_bound(hn, k):
     ix.close()
 
 
+def _int8_codes(a, amax):
+    """round(a / s) clipped to [-127, 127], s = 2^(e - 7) for amax = f 2^e,
+    0.5 <= f < 1 (numpy's rint: nearest, ties to even)."""
+    s = 1.0 if amax == 0 else math.ldexp(1.0, math.frexp(amax)[1] - 7)
+    c = np.clip(np.rint(np.asarray(a, dtype=np.float64) / s), -127, 127).astype(np.int64)
+    return s, c
+
+
+@pytest.mark.parametrize("k", [1, 8, 16, 30, 32])
+def test_scan_scores_int8_exact_and_bound(hn, k):
+    """The int8 scan score is s_q s_x times the exact integer dot of the codes
+    (bit for bit), and within the residual-norm bound of the true prefix dot."""
+    alpha = 1 / 32
+    db = hn_inputs.make_db(1007, k, alpha, 9, 700 + k)
+    qs = hn_inputs.make_queries(db, k, alpha, 28, 9, 800 + k)
+    qs[0, :k] *= 1e-3
+    say("scan_scores int8 k=%d n=1007 q=37" % k)
+    ix = hn.Index(dev(db), k, alpha, flags=hn.HN_BUILD_NO_VALIDATE)
+    got = ix.scan_scores(dev(qs), "int8").cpu().numpy()
+    sx, xc = _int8_codes(db[:, :k], float(np.abs(db[:, :k]).max()))
+    exp = np.empty((len(qs), len(db)), dtype=np.float64)
+    rq = np.empty(len(qs))
+    for i, q in enumerate(qs):
+        sq, qc = _int8_codes(q[:k], float(np.abs(q[:k]).max()))
+        exp[i] = (xc @ qc).astype(np.float64) * sq * sx
+        rq[i] = np.sqrt(((qc * sq - q[:k].astype(np.float64)) ** 2).sum())
+    assert np.array_equal(got.astype(np.float64), exp)
+    ref = qs[:, :k].astype(np.float64) @ db[:, :k].astype(np.float64).T
+    xr = xc * sx
+    rx = np.sqrt(((xr - db[:, :k]) ** 2).sum(1)).max()
+    mux = np.sqrt((xr ** 2).sum(1)).max()
+    nq = np.sqrt((qs[:, :k].astype(np.float64) ** 2).sum(1))
+    bound = rq[:, None] * mux + nq[:, None] * rx
+    assert (np.abs(got - ref) <= bound + 1e-15).all()
+    ix.close()
+
+
 # ------------------------------------------------------------ exact search
 
 def _check_search(hn, db, qs, k, alpha, precision="fp32", what="", **kw):
@@ -156,7 +193,7 @@ def test_workload1_all_precisions_exact(hn):
     db = w.db()
     qs = w.queries(db)
     bi, bs = oracle.bruteforce_top1(db, qs)
-    for prec in ("fp32", "bf16", "fp8"):
+    for prec in ("fp32", "bf16", "fp8", "int8"):
         ref, aux, st = _check_search(hn, db, qs, w.k, w.alpha, prec, "workload1")
         assert (ref["idx"] == bi).all()
         assert st["overflow_queries"] == 0
@@ -181,9 +218,9 @@ def test_edge_shapes_exact(hn, n, k, alpha, nq):
     if n >= 8:  # exact ties: duplicated rows
         db[n - 1] = db[0]
         db[n // 2] = db[3]
-    for prec in ("fp32", "bf16", "fp8"):
-        if prec == "fp8" and k > 32:
-            continue  # no fp8 copy above k = 32 (checked in test_invalid_inputs)
+    for prec in ("fp32", "bf16", "fp8", "int8"):
+        if prec in ("fp8", "int8") and k > 32:
+            continue  # no fp8 / int8 copy above k = 32 (checked in test_invalid_inputs)
         _check_search(hn, db, qs, k, alpha, prec, "edge")
 
 
@@ -195,7 +232,7 @@ def test_tie_rule_golden_on_gpu(hn):
     db[:, :4] = np.array(g["db"], dtype=np.float32)
     q = np.zeros((1, 128), dtype=np.float32)
     q[0, :4] = g["query"]
-    for prec in ("fp32", "bf16", "fp8"):
+    for prec in ("fp32", "bf16", "fp8", "int8"):
         ref, aux, _ = _check_search(hn, db, q, g["k"], g["alpha"], prec, "tie-golden",
                                     flags=hn.HN_BUILD_NO_VALIDATE)
         assert ref["idx"][0] == g["expected_idx"]
@@ -358,6 +395,11 @@ def test_bruteforce_all_identical_rows_fallback(hn):
 
 # ------------------------------------------------------------ full size
 
+def torch_equal(i1, s1, i2, s2):
+    import torch
+    return bool(torch.equal(i1, i2) and torch.equal(s1, s2))
+
+
 def test_workload2_full_size_sampled(hn):
     """N = 1,048,576, K = 16, alpha = 1/8, Q = 10,000 in the benchmark's launch
     configuration.  Every query: HN result == exhaustive GPU result and the
@@ -372,6 +414,8 @@ def test_workload2_full_size_sampled(hn):
     i32, s32, aux, st = ix.search(dq, aux=True, stats=True)
     i16, s16 = ix.search(dq, precision="bf16")
     i8, s8 = ix.search(dq, precision="fp8")
+    ii, si_ = ix.search(dq, precision="int8")
+    assert torch_equal(ii, si_, i32, s32)
     bi, bs = hn.bruteforce_top1(dev(db), dq)
     i32, s32, i16, s16, i8, s8 = (t.cpu().numpy() for t in (i32, s32, i16, s16, i8, s8))
     bi, bs = bi.cpu().numpy(), bs.cpu().numpy()
