@@ -171,6 +171,25 @@ int hn_search_top1(const hn_index *ix, const float *queries, int64_t q, int64_t 
                    hn_search_stats *stats, void *stream);
 
 /*
+ * Exact top-k (k = topk) per query: the topk entries of largest canonical
+ * sim, ordered by (sim desc, index asc) — Algorithm 1 with the running best
+ * replaced by the topk-th best.  The seed bound L is the topk-th best sim
+ * among the winning lane groups of the best scan chunks (distinct real
+ * entries, so L is at most the true topk-th best); every entry with
+ * s~ >= round_down_f32(L - alpha - eps_q) is rescored in float64 and the
+ * topk best are selected per query.  Synchronises `stream` once (and runs the
+ * filter again with a list large enough if the survivors did not fit).
+ *   topk     1 <= topk <= 128.
+ *   out_idx  device int64 [q][topk]; out_sim device double [q][topk].  Places
+ *            beyond the database size get index -1 and sim -inf; a query
+ *            with a non-finite component gets -1 and NaN throughout.
+ *   opts     precision, launch shape, survivor_cap (initial), beta; the seed
+ *            must be HN_SEED_PLAIN.
+ */
+int hn_search_topk(const hn_index *ix, const float *queries, int64_t q, int32_t topk,
+                   int64_t *out_idx, double *out_sim, const hn_search_opts *opts, void *stream);
+
+/*
  * The survivor set of the bound test for given lower bounds (Algorithm 1's
  * skip test against a fixed s_best, Eq. 3):
  *   { (q, i) : s~(q, i) >= round_down_f32(L[q] - alpha - eps_q) }.

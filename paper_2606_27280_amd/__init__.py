@@ -135,6 +135,20 @@ class Index:
             res.append({"survivors": st.survivors, "overflow_queries": st.overflow_queries})
         return tuple(res)
 
+    def search_topk(self, queries, topk, precision="fp32", query_tiles=0, chunk_blocks=0,
+                    survivor_cap=0, beta=None, stream=None):
+        """Exact top-k per query (hn_search_topk): (idx int64 [q][topk],
+        sim float64 [q][topk]) ordered by (sim desc, index asc)."""
+        torch = _torch()
+        qp = _dev(queries, torch.float32, "queries", 2)
+        q = queries.shape[0]
+        idx = torch.empty((q, int(topk)), dtype=torch.int64, device=queries.device)
+        sim = torch.empty((q, int(topk)), dtype=torch.float64, device=queries.device)
+        o = _opts(precision, query_tiles, chunk_blocks, survivor_cap, beta)
+        _lib.check(_lib.lib().hn_search_topk(self._h, qp, q, int(topk), _ptr(idx), _ptr(sim),
+                                             ctypes.byref(o), _stream(stream)))
+        return idx, sim
+
     def filter_survivors(self, queries, lower, cap, precision="fp32", beta=None, stream=None):
         """Pairs (query, entry) with scan score >= round_down(L - alpha - eps);
         returns (pairs int32 [min(count,cap)][2], count, slack float64 [q])."""

@@ -64,6 +64,7 @@ SIGNATURES = {
                              ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
     "hn_search_top1": (_i32, [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(SearchOpts),
                               ctypes.POINTER(SearchAux), ctypes.POINTER(SearchStats), _vp]),
+    "hn_search_topk": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp, ctypes.POINTER(SearchOpts), _vp]),
     "hn_filter_survivors": (_i32, [_vp, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp,
                                    ctypes.POINTER(SearchOpts), _vp]),
     "hn_scan_scores": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp]),

@@ -149,6 +149,7 @@ struct SeedArgs {
     const int32_t *part_idx;
     int32_t n_chunks, q_pad;
     int32_t part_ld;            // row stride of the partials (the argmax scan's q_pad)
+    int32_t topk;               // > 1: L is a bound on the topk-th best sim
     int32_t shape, group_size;  // scan tile shape (16 or 32) and entries per lane group
     const float *queries;
     int64_t q;
@@ -197,6 +198,100 @@ __device__ __forceinline__ int64_t group_entry(int shape, int gid, int v) {
     return (int64_t)(gid >> 1) * 32 + 8 * (v >> 2) + 4 * (gid & 1) + (v & 3);
 }
 
+// Exact top-k seed: the topk-th best canonical sim among distinct real
+// entries is a lower bound on the topk-th best sim of the query, so it bounds
+// the survivors like L does for top-1.  The entries are the winning lane
+// groups of the m best chunks, taken in (score desc, chunk asc) order, with m
+// = ceil(topk / group) + 1 (one group may hold padding).  -inf if fewer than
+// topk real entries are found.  Candidate c of the walk sits in lane c % 64,
+// slot c / 64 (at most 4 slots: topk <= 128 and 16 x 16 groups are 4 wide).
+__device__ __noinline__ double topk_lower(const SeedArgs &S, const int64_t i, const int lane,
+                                          const float *qv) {
+    const int gs = S.group_size;
+    const int m = min(S.n_chunks, (S.topk + gs - 1) / gs + 1);
+    double cs[4];
+    int64_t ce[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        cs[t] = -INFINITY;
+        ce[t] = -1;
+    }
+    int used = 0;  // slots this lane has filled
+    float pv = INFINITY;
+    int pc = -1;
+    for (int r = 0; r < m; ++r) {
+        // the next chunk after (pv, pc) in (score desc, chunk asc) order
+        float bv = -INFINITY;
+        int bc = -1;
+        for (int c = lane; c < S.n_chunks; c += 64) {
+            const float v = S.part_val[(int64_t)c * S.part_ld + i];
+            const bool after = v < pv || (v == pv && c > pc);
+            if (after && (bc < 0 || v > bv)) {
+                bv = v;
+                bc = c;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const float ov = __shfl_xor(bv, o);
+            const int oc = __shfl_xor(bc, o);
+            if (oc >= 0 && (bc < 0 || ov > bv || (ov == bv && oc < bc))) {
+                bv = ov;
+                bc = oc;
+            }
+        }
+        bc = __builtin_amdgcn_readfirstlane(bc);
+        if (bc < 0) break;
+        pv = bv;
+        pc = bc;
+        const int gid = S.part_idx[(int64_t)bc * S.part_ld + i];
+        if (gid < 0) continue;
+        // candidates r * gs .. r * gs + gs - 1 of the walk
+        const int t = (lane - (r * gs) % 64 + 64) % 64;
+        if (t < gs) {
+            const int64_t e = group_entry(S.shape, gid, t);
+            const double sv = e < S.n ? sim64(qv, S.rows + e * kDim) : -INFINITY;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u == used) {
+                    cs[u] = sv;
+                    ce[u] = e < S.n ? e : -1;
+                }
+            ++used;
+        }
+    }
+    // the topk-th of the candidates in (sim desc, entry asc) order
+    unsigned popped = 0;
+    double L = -INFINITY;
+    for (int r = 0; r < S.topk; ++r) {
+        double bv = -INFINITY;
+        int64_t be = -1;
+        int bs = -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if ((popped >> u) & 1u || ce[u] < 0) continue;
+            if (be < 0 || cs[u] > bv || (cs[u] == bv && ce[u] < be)) {
+                bv = cs[u];
+                be = ce[u];
+                bs = u;
+            }
+        }
+        double wv = bv;
+        int64_t we = be;
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(wv, o);
+            const int64_t oe = __shfl_xor(we, o);
+            if (oe >= 0 && (we < 0 || ov > wv || (ov == wv && oe < we))) {
+                wv = ov;
+                we = oe;
+            }
+        }
+        if (__builtin_amdgcn_readfirstlane((int)(we >= 0)) == 0) return -INFINITY;
+        if (be == we && bs >= 0) popped |= 1u << bs;  // the owner lane pops it
+        L = wv;
+    }
+    return L;
+}
+
 // Query i, one wave: reduce the per-chunk argmax partials, rescore every
 // entry of the winning lane group in float64 (one lane each) and keep the
 // best (sim desc, index asc) as the seed; then the slack and thresholds.
@@ -238,6 +333,8 @@ __device__ __forceinline__ void seed_one(const SeedArgs &S, const int64_t i, con
     if (S.lower) {
         L = S.lower[i];
         b = S.lower_idx ? S.lower_idx[i] : -1;
+    } else if (S.topk > 1) {
+        L = topk_lower(S, i, lane, qv);
     } else {
         float bv = -INFINITY;
         int bi = -1;
@@ -622,6 +719,101 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs F) {
     if (F.aux.threshold) F.aux.threshold[o] = F.thr ? F.thr[i] : (float)NAN;
     if (F.aux.slack) F.aux.slack[o] = F.slack ? F.slack[i] : (double)NAN;
     if (F.n_flagged && F.qflag[i]) atomicAdd(F.n_flagged, 1ull);
+}
+
+// ------------------------------------------------------------ exact top-k
+
+// Exclusive prefix sums of per-query counts, off[q] = total (one work-group,
+// 1024 queries at a time; the loop bound is uniform).
+__global__ __launch_bounds__(1024) void prefix_counts(const int32_t *__restrict__ cnt, int64_t q,
+                                                      int64_t *__restrict__ off) {
+    __shared__ int64_t sh[1024];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < q; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < q ? cnt[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int64_t add = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < q) off[i] = carry + sh[threadIdx.x] - v;
+        carry += sh[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[q] = carry;
+}
+
+// Bucket the rescored pairs by query (order inside a bucket is arbitrary).
+__global__ __launch_bounds__(256) void scatter_pairs(const int2 *__restrict__ pairs,
+                                                     const unsigned long long *counter, int64_t cap,
+                                                     const int64_t *__restrict__ off,
+                                                     int32_t *__restrict__ fill,
+                                                     int32_t *__restrict__ seg) {
+    const unsigned long long c = *counter;
+    const int64_t m = (int64_t)c < cap ? (int64_t)c : cap;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < m;
+         p += (int64_t)gridDim.x * 256) {
+        const int q = pairs[p].x;
+        seg[off[q] + atomicAdd(&fill[q], 1)] = (int32_t)p;
+    }
+}
+
+// One wave per query: the topk best of its bucket in (sim desc, entry asc)
+// order, by topk sweeps that each take the best pair after the previous one
+// (the order is total, so the result does not depend on the bucket order).
+// Missing places (fewer entries than topk) get index -1 and sim -inf; a query
+// with a non-finite component gets -1 and NaN.
+__global__ __launch_bounds__(256) void topk_select(const int64_t *__restrict__ off,
+                                                   const int32_t *__restrict__ seg,
+                                                   const int2 *__restrict__ pairs,
+                                                   const double *__restrict__ psim, int64_t q,
+                                                   int topk, const QNorm *__restrict__ qn,
+                                                   int64_t *__restrict__ out_idx,
+                                                   double *__restrict__ out_sim) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= q) return;
+    const bool bad = qn[i].bad != 0;
+    const int64_t lo = off[i], hi = off[i + 1];
+    double pv = INFINITY;
+    int64_t pe = -1;
+    bool done = bad;
+    for (int r = 0; r < topk; ++r) {
+        double bv = -INFINITY;
+        int64_t be = -1;
+        if (!done) {
+            for (int64_t j = lo + lane; j < hi; j += 64) {
+                const int p = seg[j];
+                const double s = psim[p];
+                if (s == -INFINITY) continue;
+                const int64_t e = pairs[p].y;
+                const bool after = s < pv || (s == pv && e > pe);
+                if (after && (be < 0 || s > bv || (s == bv && e < be))) {
+                    bv = s;
+                    be = e;
+                }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(bv, o);
+                const int64_t oe = __shfl_xor(be, o);
+                if (oe >= 0 && (be < 0 || ov > bv || (ov == bv && oe < be))) {
+                    bv = ov;
+                    be = oe;
+                }
+            }
+            done = be < 0;
+        }
+        if (lane == 0) {
+            out_idx[i * topk + r] = bad ? -1 : be;
+            out_sim[i * topk + r] = bad ? (double)NAN : (be < 0 ? -INFINITY : bv);
+        }
+        pv = bv;
+        pe = be;
+    }
 }
 
 // ------------------------------------------------- brute-force helpers

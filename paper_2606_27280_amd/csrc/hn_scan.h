@@ -334,7 +334,9 @@ __device__ __forceinline__ void flush_pairs(const ScanArgs &A, EmitBuf &B) {
 }
 
 // Append the lane's entries with score >= t, in groups of 4 accumulator
-// slots: ballot per slot, positions by popcount + mbcnt prefix counts.
+// slots: ballot per slot, positions by popcount + mbcnt prefix counts.  Rows
+// past the database end are never appended (their scores are -inf, which a
+// threshold of -inf would otherwise accept).
 template <class Tile, bool WithVal, bool Direct>
 __device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B,
                                            const typename Tile::Acc &a, float t, bool qvalid,
@@ -348,7 +350,7 @@ __device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B,
         int total = 0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            pv[u] = qvalid && a[v0 + u] >= t;
+            pv[u] = qvalid && a[v0 + u] >= t && eblk + Tile::out_row(lane, v0 + u) < A.n;
             mv[u] = __ballot(pv[u]);
             c[u] = __popcll(mv[u]);
             total += c[u];

@@ -96,7 +96,7 @@ int validate_opts(const hn_index *ix, const hn_search_opts *o) {
 // (W.win, W.win_scan, W.init_best) and the pair values.
 int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_search_opts &o,
                const double *lower, const int64_t *lower_idx, int64_t cap, Work &W,
-               hipStream_t s, bool window = false) {
+               hipStream_t s, bool window = false, int topk = 0) {
     W.precision = o.precision;
     W.width = stream_width(ix, W.precision);
     W.stream_x = stream_of(ix, W.precision);
@@ -234,6 +234,7 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     S.n_chunks = sp.n_chunks;
     S.q_pad = (int32_t)qp;
     S.part_ld = (int32_t)sp.q_pad;
+    S.topk = topk;
     S.shape = W.shape;
     S.group_size = W.shape == 16 ? 4 : 16;
     S.queries = queries;
@@ -322,6 +323,11 @@ namespace {
 
 // Survivor-list budget per query of the single-pass forms (the window keeps
 // more pairs than the two-pass threshold) and the query batch that fits it.
+__global__ void fill_i32(int32_t *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = 0;
+}
+
 int64_t window_per_query(int64_t n) { return std::max<int64_t>(8192, n / 32); }
 int64_t window_batch(int64_t n) {
     return std::max<int64_t>(256, ((int64_t)1 << 29) / window_per_query(n));
@@ -589,6 +595,85 @@ extern "C" int hn_search_top1(const hn_index *ix, const float *queries, int64_t 
             stats->overflow_queries += st.overflow_queries;
         }
     }
+    return HN_OK;
+}
+
+extern "C" int hn_search_topk(const hn_index *ix, const float *queries, int64_t q, int32_t topk,
+                              int64_t *out_idx, double *out_sim, const hn_search_opts *opts,
+                              void *stream) {
+    clear_error();
+    if (!ix) return fail(HN_ERR_INVALID_ARG, "null index");
+    if (topk < 1 || topk > 128) return fail(HN_ERR_INVALID_ARG, "topk must be in [1, 128]");
+    if (q < 0) return fail(HN_ERR_INVALID_ARG, "q must be >= 0");
+    if (q >= ((int64_t)1 << 31) - 4096) return fail(HN_ERR_UNSUPPORTED, "q must be < 2^31");
+    if (q > 0 && (!queries || !out_idx || !out_sim))
+        return fail(HN_ERR_INVALID_ARG, "null queries or outputs");
+    int rc = validate_opts(ix, opts);
+    if (rc) return rc;
+    if (q == 0) return HN_OK;
+    const hn_search_opts o =
+        opts ? *opts : hn_search_opts{HN_PREC_FP32, HN_SEED_PLAIN, 0, 0, 0, -1.0};
+    if (o.seed != HN_SEED_PLAIN) return fail(HN_ERR_UNSUPPORTED, "top-k uses the plain seed");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t cap = o.survivor_cap > 0 ? o.survivor_cap : default_cap(ix->n, q);
+    Work W;
+    unsigned long long total = 0;
+    // The survivor set is fixed by the seeds; if it did not fit, run again
+    // with room for all of it (the counter keeps counting past the cap).
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        rc = stage_seed(ix, queries, q, o, nullptr, nullptr, cap, W, s, false, topk);
+        if (rc) return rc;
+        ScanArgs A = filter_args(ix, W, q, W.pairs, cap);
+        rc = launch_scan<kFilter>(W.precision, W.width, W.cfg, W.plan, A, s);
+        if (rc) return rc;
+        RescoreArgs R;
+        memset(&R, 0, sizeof R);
+        R.pairs = W.pairs;
+        R.counter = W.counter;
+        R.cap = cap;
+        R.queries = queries;
+        R.rows = ix->rows;
+        R.major32 = ix->major32;
+        R.kp = ix->kp;
+        R.k = ix->k;
+        R.thr32 = W.thr32;
+        R.psim = W.psim;
+        R.best_key = W.best_key;
+        R.best_idx = W.best_idx;
+        R.cnt = W.cnt;
+        R.q = q;
+        R.count = 1;
+        {
+            ProfScope prof_(s, "topk_rescore");
+            if (W.precision == HN_PREC_FP32)
+                hipLaunchKernelGGL(rescore_kernel<0>, dim3(2048), dim3(256), 0, s, R);
+            else
+                hipLaunchKernelGGL(rescore_kernel<1>, dim3(2048), dim3(256), 0, s, R);
+        }
+        HN_HIP(hipMemcpyAsync(&total, W.counter, sizeof total, hipMemcpyDeviceToHost, s));
+        HN_HIP(hipStreamSynchronize(s));
+        if ((int64_t)total <= cap) break;
+        if (attempt == 1) return fail(HN_ERR_DEVICE, "top-k survivor list grew between passes");
+        if (total >= ((unsigned long long)1 << 31))
+            return fail(HN_ERR_UNSUPPORTED, "top-k needs %llu survivor pairs (limit 2^31)", total);
+        cap = (int64_t)total;
+    }
+    Arena *ar = nullptr;
+    rc = arena_for((void *)s, (size_t)(q + 1) * 8 + (size_t)q * 4 + (size_t)cap * 4 + 1024, &ar, 3);
+    if (rc) return rc;
+    int64_t *off = ar->take<int64_t>(q + 1);
+    int32_t *fill = ar->take<int32_t>(q);
+    int32_t *seg = ar->take<int32_t>(cap);
+    hipLaunchKernelGGL(fill_i32, dim3(blocks_for(q)), dim3(256), 0, s, fill, q);
+    {
+        ProfScope prof_(s, "topk_select");
+        hipLaunchKernelGGL(prefix_counts, dim3(1), dim3(1024), 0, s, W.cnt, q, off);
+        hipLaunchKernelGGL(scatter_pairs, dim3(2048), dim3(256), 0, s, W.pairs, W.counter, cap, off,
+                           fill, seg);
+        hipLaunchKernelGGL(topk_select, dim3(blocks_for(q, 4)), dim3(256), 0, s, off, seg, W.pairs,
+                           W.psim, q, topk, W.qn, out_idx, out_sim);
+    }
+    HN_HIP(hipGetLastError());
     return HN_OK;
 }
 

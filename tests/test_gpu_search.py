@@ -482,3 +482,19 @@ def test_soft_beta_mode(hn, frac):
     recall = float((si == ei).mean())
     say("recall@1 at beta=%g: %.3f" % (beta, recall))
     ix.close()
+
+
+def test_filter_lower_minus_inf_ragged(hn):
+    """L = -inf keeps every real entry and nothing past the database end
+    (a size that is not a multiple of the scan's row blocks)."""
+    import torch
+    db = hn_inputs.make_db(1001, 16, 1 / 8, 10, 5150)
+    qs = hn_inputs.make_queries(db, 16, 1 / 8, 5, 0, 5151)
+    ix = hn.Index(dev(db), 16, 1 / 8)
+    lo = torch.full((5,), -math.inf, dtype=torch.float64, device="cuda:0")
+    say("filter with L = -inf, n = 1001")
+    for prec in ("fp32", "bf16", "int8"):
+        pairs, c_all, _ = ix.filter_survivors(dev(qs), lo, cap=1 << 16, precision=prec)
+        assert c_all == 5 * 1001
+        assert int(pairs[:, 1].max()) == 1000
+    ix.close()

@@ -1,0 +1,92 @@
+"""GPU parity of the exact top-k search against the oracle's exhaustive
+top-k (float64 canonical sims, ordered by (sim desc, index asc)), through the
+C ABI: indices bit-exact, sims within 1e-12 (equal in practice)."""
+import numpy as np
+import pytest
+
+import hn_inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+SIM_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def hn():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2606_27280_amd as hn
+    hn._lib.lib()
+    return hn
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def check(idx, sim, ri, rs, what):
+    idx = idx.cpu().numpy()
+    sim = sim.cpu().numpy()
+    bad = np.argwhere(idx != ri)
+    assert bad.size == 0, "%s: first mismatch at %s: %d vs %d" % (
+        what, bad[0], idx[tuple(bad[0])], ri[tuple(bad[0])])
+    fin = np.isfinite(rs)
+    assert (np.abs(sim[fin] - rs[fin]) <= SIM_TOL).all(), what
+    assert (sim[~fin] == rs[~fin]).all(), what
+
+
+@pytest.mark.parametrize("topk", [1, 5, 16, 40, 128])
+def test_topk_matches_oracle(hn, topk):
+    w = hn_inputs.workload(1)
+    db = w.db()
+    qs = w.queries(db)[:96]
+    db[100] = db[7]  # an exact tie: the smaller index comes first
+    ri, rs = oracle.topk(db, qs, topk)
+    ix = hn.Index(dev(db), w.k, w.alpha)
+    for prec in ("fp32", "bf16", "int8"):
+        say("top-%d %s" % (topk, prec))
+        idx, sim = ix.search_topk(dev(qs), topk, precision=prec)
+        check(idx, sim, ri, rs, "top-%d %s" % (topk, prec))
+    if topk == 1:
+        i1, s1 = ix.search(dev(qs))
+        assert (i1.cpu().numpy() == ri[:, 0]).all()
+    ix.close()
+
+
+@pytest.mark.parametrize("n,k,alpha,topk", [(5, 16, 1 / 8, 16), (40, 8, 1 / 32, 32),
+                                            (3000, 64, 1 / 4, 20), (2500, 16, 0.0, 7)])
+def test_topk_edge_shapes(hn, n, k, alpha, topk):
+    db = hn_inputs.make_db(n, k, alpha, max(1, n // 64), 4000 + n)
+    qs = hn_inputs.make_queries(db, k, alpha, 25, 8, 4100 + n)
+    ri, rs = oracle.topk(db, qs, topk)
+    say("top-%d n=%d k=%d alpha=%g" % (topk, n, k, alpha))
+    ix = hn.Index(dev(db), k, alpha)
+    idx, sim = ix.search_topk(dev(qs), topk)
+    check(idx, sim, ri, rs, "edge")
+    ix.close()
+
+
+def test_topk_small_list_second_pass_and_errors(hn):
+    w = hn_inputs.workload(1)
+    db = w.db()
+    qs = w.queries(db)[:40]
+    ri, rs = oracle.topk(db, qs, 10)
+    ix = hn.Index(dev(db), w.k, w.alpha)
+    say("top-10 with survivor_cap=100 (second pass)")
+    idx, sim = ix.search_topk(dev(qs), 10, survivor_cap=100)
+    check(idx, sim, ri, rs, "small list")
+    q2 = qs.copy()
+    q2[3, 0] = np.nan
+    idx, sim = ix.search_topk(dev(q2), 4)
+    assert (idx.cpu().numpy()[3] == -1).all() and np.isnan(sim.cpu().numpy()[3]).all()
+    with pytest.raises(hn.HNError):
+        ix.search_topk(dev(qs), 0)
+    with pytest.raises(hn.HNError):
+        ix.search_topk(dev(qs), 129)
+    ix.close()
