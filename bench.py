@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--epochs", type=int, default=4, help="seed-model training epochs")
     ap.add_argument("--batch", type=int, default=1024, help="seed-model training batch")
     ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--topk", type=int, default=0,
+                    help="also time exact top-k (hn_search_topk) at this k")
     ap.add_argument("--beta-sweep", action="store_true",
                     help="also time the soft mode (Section 7) at beta = alpha x {3/4, 1/2, "
                          "1/4, 0}: recall@1 against the exact result and pruned fraction")
@@ -500,6 +502,17 @@ def main():
                                "pruned_pct": round(float(
                                    100.0 * (1.0 - ba["survivors"].double().mean() / w.n)), 4)})
         log("beta sweep: %s" % beta_sweep)
+    topk_res = None
+    if args.topk:
+        kt = args.topk
+        ti, ts = ix.search_topk(d_q, kt, precision=args.precision)
+        first_equal = bool(torch.equal(ti[:, 0], idx) and torch.equal(ts[:, 0], sim))
+        tk, _ = timed(lambda: ix.search_topk(d_q, kt, precision=args.precision), args.steps, 1,
+                      torch)
+        topk_res = {"k": kt, "queries_per_s": round(Q * args.steps / tk, 1),
+                    "ms_per_step": round(1e3 * tk / args.steps, 4),
+                    "first_column_equals_top1": first_equal}
+        log("top-%d: %s" % (kt, topk_res))
     seed_forms = {}
     if seed_report is not None:
         # every seed form at the timed precision: queries/s, first-pass
@@ -550,6 +563,8 @@ def main():
         res["seed_forms"] = seed_forms
     if beta_sweep:
         res["beta_sweep"] = beta_sweep
+    if topk_res is not None:
+        res["topk"] = topk_res
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(db, qs, w.k, w.alpha, args.cpu_seconds)

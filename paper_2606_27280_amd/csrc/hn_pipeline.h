@@ -198,27 +198,23 @@ __device__ __forceinline__ int64_t group_entry(int shape, int gid, int v) {
     return (int64_t)(gid >> 1) * 32 + 8 * (v >> 2) + 4 * (gid & 1) + (v & 3);
 }
 
-// Exact top-k seed: the topk-th best canonical sim among distinct real
-// entries is a lower bound on the topk-th best sim of the query, so it bounds
-// the survivors like L does for top-1.  The entries are the winning lane
-// groups of the m best chunks, taken in (score desc, chunk asc) order, with m
-// = ceil(topk / group) + 1 (one group may hold padding).  -inf if fewer than
-// topk real entries are found.  Candidate c of the walk sits in lane c % 64,
-// slot c / 64 (at most 4 slots: topk <= 128 and 16 x 16 groups are 4 wide).
-__device__ __noinline__ double topk_lower(const SeedArgs &S, const int64_t i, const int lane,
+// Exact top-k seed: the topk-th largest of distinct real entries' canonical
+// sims is at most the query's topk-th best sim, so it bounds the survivors
+// like L does for top-1.  The entries: for each of the m = min(chunks,
+// 2 topk) best chunks, in (score desc, chunk asc) order, the best sim of its
+// winning lane group (the group holds the chunk's largest scan score, so
+// these are the near-best entries of distinct chunks).  -inf if fewer than
+// topk such entries exist.  Chunk r's value sits in lane r % 64, slot r / 64.
+__device__ __forceinline__ double topk_lower(const SeedArgs &S, const int64_t i, const int lane,
                                           const float *qv) {
     const int gs = S.group_size;
-    const int m = min(S.n_chunks, (S.topk + gs - 1) / gs + 1);
+    const int m = min(S.n_chunks, min(2 * S.topk, 256));
     double cs[4];
-    int64_t ce[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        cs[t] = -INFINITY;
-        ce[t] = -1;
-    }
-    int used = 0;  // slots this lane has filled
+    for (int t = 0; t < 4; ++t) cs[t] = -INFINITY;
     float pv = INFINITY;
     int pc = -1;
+    int found = 0;  // chunks with a real entry
     for (int r = 0; r < m; ++r) {
         // the next chunk after (pv, pc) in (score desc, chunk asc) order
         float bv = -INFINITY;
@@ -244,49 +240,40 @@ __device__ __noinline__ double topk_lower(const SeedArgs &S, const int64_t i, co
         pv = bv;
         pc = bc;
         const int gid = S.part_idx[(int64_t)bc * S.part_ld + i];
-        if (gid < 0) continue;
-        // candidates r * gs .. r * gs + gs - 1 of the walk
-        const int t = (lane - (r * gs) % 64 + 64) % 64;
-        if (t < gs) {
-            const int64_t e = group_entry(S.shape, gid, t);
-            const double sv = e < S.n ? sim64(qv, S.rows + e * kDim) : -INFINITY;
+        double sv = -INFINITY;
+        if (gid >= 0 && lane < gs) {
+            const int64_t e = group_entry(S.shape, gid, lane);
+            if (e < S.n) sv = sim64(qv, S.rows + e * kDim);
+        }
+        for (int o = 32; o > 0; o >>= 1) sv = fmax(sv, __shfl_xor(sv, o));
+        if (sv == -INFINITY) continue;
+        if (lane == found % 64) {
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (u == used) {
-                    cs[u] = sv;
-                    ce[u] = e < S.n ? e : -1;
-                }
-            ++used;
+                if (u == found / 64) cs[u] = sv;
         }
+        ++found;
     }
-    // the topk-th of the candidates in (sim desc, entry asc) order
-    unsigned popped = 0;
+    if (found < S.topk) return -INFINITY;
+    // the topk-th largest value: topk pops of the wave maximum, one copy each
     double L = -INFINITY;
     for (int r = 0; r < S.topk; ++r) {
-        double bv = -INFINITY;
-        int64_t be = -1;
-        int bs = -1;
+        double mv = -INFINITY;
+        int ms = -1;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if ((popped >> u) & 1u || ce[u] < 0) continue;
-            if (be < 0 || cs[u] > bv || (cs[u] == bv && ce[u] < be)) {
-                bv = cs[u];
-                be = ce[u];
-                bs = u;
+        for (int u = 0; u < 4; ++u)
+            if (cs[u] > mv) {
+                mv = cs[u];
+                ms = u;
             }
+        double wv = mv;
+        for (int o = 32; o > 0; o >>= 1) wv = fmax(wv, __shfl_xor(wv, o));
+        const unsigned long long owners = __ballot(ms >= 0 && mv == wv);
+        if ((int)lane == __builtin_ffsll((long long)owners) - 1) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (u == ms) cs[u] = -INFINITY;
         }
-        double wv = bv;
-        int64_t we = be;
-        for (int o = 32; o > 0; o >>= 1) {
-            const double ov = __shfl_xor(wv, o);
-            const int64_t oe = __shfl_xor(we, o);
-            if (oe >= 0 && (we < 0 || ov > wv || (ov == wv && oe < we))) {
-                wv = ov;
-                we = oe;
-            }
-        }
-        if (__builtin_amdgcn_readfirstlane((int)(we >= 0)) == 0) return -INFINITY;
-        if (be == we && bs >= 0) popped |= 1u << bs;  // the owner lane pops it
         L = wv;
     }
     return L;

@@ -117,6 +117,10 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
         return fail(HN_ERR_INVALID_ARG, "query_tiles=%d is not available for this width",
                     o.query_tiles);
     W.seed_plan = make_plan(ix->n, q, W.seed_cfg, o.chunk_blocks, tis.rows, tis.cols);
+    // top-k seeds take the best of up to 2 topk chunks: plan at least that many
+    if (topk > 1 && o.chunk_blocks == 0 && W.seed_plan.n_chunks < 2 * topk)
+        W.seed_plan = make_plan(ix->n, q, W.seed_cfg, 0, tis.rows, tis.cols,
+                                (int64_t)W.seed_plan.n_qb * 2 * topk);
     W.shape = tis.rows;
     const Plan &sp = W.seed_plan;
     const int64_t qp = std::max(p.q_pad, sp.q_pad);
