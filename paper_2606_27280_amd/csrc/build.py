@@ -14,6 +14,9 @@ SOURCES = ["hn_index.hip", "hn_search.hip", "hn_profile.hip", "hn_scan_f32n.hip"
 OUT = os.path.join(PKG, "libhnsearch.so")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA results in ordinary VGPRs: the epilogues read every score, and
+         # the accumulation-register form costs one copy instruction per score
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I", os.path.join(ROOT, "include"), "-I", HERE]
 
 

@@ -342,6 +342,7 @@ __device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B,
                                            const typename Tile::Acc &a, float t, bool qvalid,
                                            int q, int eblk) {
     const int lane = (int)__lane_id();
+    const int rows_left = (int)min<int64_t>(A.n - eblk, (int64_t)Tile::kRows);
 #pragma unroll
     for (int v0 = 0; v0 < Tile::kAcc; v0 += 4) {
         bool pv[4];
@@ -350,7 +351,7 @@ __device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B,
         int total = 0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            pv[u] = qvalid && a[v0 + u] >= t && eblk + Tile::out_row(lane, v0 + u) < A.n;
+            pv[u] = qvalid && a[v0 + u] >= t && Tile::out_row(lane, v0 + u) < rows_left;
             mv[u] = __ballot(pv[u]);
             c[u] = __popcll(mv[u]);
             total += c[u];
