@@ -10,7 +10,8 @@ ROOT = os.path.dirname(PKG)
 SOURCES = ["hn_index.hip", "hn_search.hip", "hn_profile.hip", "hn_scan_f32n.hip",
            "hn_scan_f32w.hip", "hn_scan_bf16.hip", "hn_scan_fp8.hip", "hn_seed.hip",
            "hn_scan_multi.hip", "hn_multi.hip", "hn_layer.hip",
-           "hn_scan_i8.hip"]
+           "hn_scan_i8.hip", "hn_scan_multi_f32.hip", "hn_scan_multi_bf16.hip",
+           "hn_scan_multi_fp8.hip", "hn_scan_multi_i8.hip"]
 OUT = os.path.join(PKG, "libhnsearch.so")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-function", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -25,34 +26,30 @@ def build(verbose: bool = False) -> str:
     os.makedirs(objdir, exist_ok=True)
 
     def compile_one(src):
-        obj = os.path.join(objdir, src + ".o")
-        cmd = ["hipcc", *FLAGS, "-c", os.path.join(HERE, src), "-o", obj]
+        # one compile per source; -save-temps keeps the device assembly, which
+        # is checked for barriers inside divergent loops
+        d = os.path.join(objdir, os.path.splitext(src)[0])
+        os.makedirs(d, exist_ok=True)
+        obj = os.path.join(d, src + ".o")
+        cmd = ["hipcc", *FLAGS, "-c", os.path.join(HERE, src), "-o", obj, "-save-temps=obj"]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr[-6000:]))
         if verbose and r.stderr.strip():
             sys.stderr.write(r.stderr)
-        return obj
-
-    def check_one(src):
-        # device assembly, checked for barriers inside divergent loops
-        asm = os.path.join(objdir, src + ".s")
-        cmd = ["hipcc", *FLAGS, "-S", "--cuda-device-only", os.path.join(HERE, src), "-o", asm]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError("hipcc -S failed for %s:\n%s" % (src, r.stderr[-6000:]))
+        asm = os.path.join(d, os.path.splitext(src)[0] + "-hip-amdgcn-amd-amdhsa-gfx950.s")
+        if not os.path.exists(asm):
+            raise RuntimeError("no device assembly for %s" % src)
         r = subprocess.run([sys.executable, os.path.join(HERE, "check_barriers.py"), asm, "-v"],
                            capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("barrier check failed for %s:\n%s" % (src, r.stdout[-4000:]))
-        return asm
+        return obj
 
-    with ThreadPoolExecutor(max_workers=min(8, 2 * len(SOURCES))) as ex:
-        futs = [ex.submit(compile_one, s) for s in SOURCES]
-        checks = [ex.submit(check_one, s) for s in SOURCES]
-        objs = [f.result() for f in futs]
-        for c in checks:
-            c.result()
+    # the scan units dominate: start them first
+    order = sorted(SOURCES, key=lambda f: not f.startswith("hn_scan"))
+    with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+        objs = list(ex.map(compile_one, order))
     tmp = OUT + ".tmp%d" % os.getpid()
     subprocess.check_call(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs,
                            "-o", tmp])

@@ -892,5 +892,14 @@ int launch_scan_int8(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
 int launch_scan_multi(int precision, int mode, int w, int cfg, const ScanArgs *dbs,
                       const int2 *items, int n_items, const int *redo,
                       const unsigned *redo_count, hipStream_t s);
+#define HN_MULTI_DECL(name)                                                                    \
+    int launch_scan_multi_##name(int mode, int w, int cfg, const ScanArgs *dbs,             \
+                                 const int2 *items, int n_items, const int *redo,          \
+                                 const unsigned *redo_count, hipStream_t s);
+HN_MULTI_DECL(f32)   // widths 8, 16, 32
+HN_MULTI_DECL(bf16)  // widths 16, 32
+HN_MULTI_DECL(fp8)   // widths 16, 32
+HN_MULTI_DECL(i8)    // widths 16, 32
+#undef HN_MULTI_DECL
 
 }  // namespace hn
