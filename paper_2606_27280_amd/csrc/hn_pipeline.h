@@ -910,6 +910,17 @@ const char *scan_tag(int mode, int precision) {
                                                   : 3];
 }
 
+// Resident work-groups of the scan kernel launch_scan<mode> would start (0 if
+// not compiled): the slot count that make_plan balances the items over.
+inline int64_t scan_slots(int precision, int mode, int w, int cfg) {
+    if (precision == HN_PREC_FP32)
+        return w <= 32 ? slots_scan_f32_narrow(mode, w, cfg) : slots_scan_f32_wide(mode, w, cfg);
+    if (precision == HN_PREC_BF16) return slots_scan_bf16(mode, w, cfg);
+    if (precision == HN_PREC_FP8) return slots_scan_fp8(mode, w, cfg);
+    if (precision == HN_PREC_INT8) return slots_scan_int8(mode, w, cfg);
+    return 0;
+}
+
 template <int MODE>
 int launch_scan(int precision, int w, int cfg, const Plan &p, const ScanArgs &A,
                 hipStream_t s) {

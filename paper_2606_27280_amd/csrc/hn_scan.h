@@ -99,11 +99,36 @@ struct Regs {  // N consecutive 32-bit values, loaded with the widest loads
             }
         }
     }
+    // The same values through a buffer descriptor: `off` is a byte offset
+    // from the descriptor's base; the hardware returns zeros for bytes past
+    // its range instead of reading them.
+    __device__ __forceinline__ void load_buf(__amdgpu_buffer_rsrc_t r, int off) {
+        if constexpr (N == 1) {
+            v[0] = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+        } else if constexpr (N == 2) {
+            const auto a = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+            v[0] = a[0];
+            v[1] = a[1];
+        } else {
+#pragma unroll
+            for (int c = 0; c < N / 4; ++c) {
+                const auto a = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16 * c, 0, 0);
+                v[4 * c + 0] = a[0];
+                v[4 * c + 1] = a[1];
+                v[4 * c + 2] = a[2];
+                v[4 * c + 3] = a[3];
+            }
+        }
+    }
     __device__ __forceinline__ void zero() {
 #pragma unroll
         for (int i = 0; i < N; ++i) v[i] = 0u;
     }
 };
+
+// Fourth word of a raw (unstructured, stride 0) buffer descriptor on CDNA:
+// 32-bit data format, no swizzle.
+constexpr int kRawBufferWord3 = 0x00020000;
 
 // The query operand of a tile is held as loaded (QFrag = Frag) unless the
 // tile decodes it once at load time.
@@ -303,7 +328,11 @@ __device__ __forceinline__ float acc_max(const Acc &a) {
 // global list with one atomic per wave at the end of the work item.  A wave
 // whose buffer fills marks the item for a re-run by scan_redo_kernel, which
 // flushes whenever its buffer fills (Direct); the set of pairs is the same.
-constexpr int kEmitCap = 1024;  // pairs per wave buffer (>= 64 lanes x 4 slots)
+#ifndef HN_EMIT_CAP
+#define HN_EMIT_CAP 1024
+#endif
+constexpr int kEmitCap = HN_EMIT_CAP;  // pairs per wave buffer (>= 64 lanes x 4 slots)
+static_assert(kEmitCap >= 256, "a flush must always fit four ballots of 64 lanes");
 
 struct EmitBuf {
     int2 *pairs;  // LDS [kEmitCap]
@@ -429,8 +458,18 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
 
     const int blk0 = chunk * A.chunk_blocks;
     const int blk1 = min(blk0 + A.chunk_blocks, A.n_blocks);
-    const int64_t last_row = A.n - 1;
-    const Elem *xcol = xs + g * Tile::kSlice;
+    // The item's entry rows through one buffer descriptor based at its first
+    // row and ending at its last row (or the database end): a block's load
+    // is the lane's fixed byte offset plus the block's, with no per-lane
+    // address arithmetic, and rows past the database end read as zeros.
+    // make_plan keeps a chunk below 2^31 bytes.
+    const int64_t row0 = (int64_t)blk0 * R;
+    const int row_bytes = A.x_stride * (int)sizeof(Elem);
+    const int64_t rows_in = min((int64_t)blk1 * R, A.n) - row0;
+    const __amdgpu_buffer_rsrc_t xrsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(xs + row0 * A.x_stride), (short)0, (int)(rows_in * row_bytes), kRawBufferWord3);
+    const int lane_off = r * row_bytes + g * Tile::kSlice * (int)sizeof(Elem);
+    const int full_blocks = (int)(A.n / R);  // blocks with no row past the end
     // Two register groups of PF entry blocks each: while one group is being
     // computed the other one is loading.  Every slot is loaded on every step
     // (past the item's end the address is clamped to its last block), so the
@@ -441,7 +480,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
             const int b = min(gbase + j * NS, blk_last);
-            xg[j].load(xcol + min((int64_t)b * R + r, last_row) * A.x_stride);
+            xg[j].load_buf(xrsrc, lane_off + (b - blk0) * (R * row_bytes));
         }
     };
     auto compute_group = [&](const Frag (&xg)[PF], int gbase) {
@@ -453,7 +492,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
 #pragma unroll
             for (int t = 0; t < NQ; ++t) acc[t] = Tile::mma(xg[j], qf[t]);
             const int eblk = blk * R;
-            if ((int64_t)eblk + R > A.n) {
+            if (blk >= full_blocks) {
 #pragma unroll
                 for (int t = 0; t < NQ; ++t)
 #pragma unroll
@@ -609,8 +648,15 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
 // L2.  The item loop depends only on blockIdx and gridDim: it is uniform, so
 // the barriers inside scan_item are reached by every wave the same number of
 // times.
+// Optional occupancy request for the scan kernels (waves per SIMD).
+#ifdef HN_WAVES_PER_EU
+#define HN_SCAN_ATTR __attribute__((amdgpu_waves_per_eu(HN_WAVES_PER_EU)))
+#else
+#define HN_SCAN_ATTR
+#endif
+
 template <class Tile, int NQ, int WQ, int MODE>
-__global__ __launch_bounds__(256) void scan_kernel(ScanArgs A) {
+__global__ __launch_bounds__(256) HN_SCAN_ATTR void scan_kernel(ScanArgs A) {
     HN_SCAN_SHARED(Tile, NQ, MODE)
     const int groups_per_xcd = (int)gridDim.x / kXcds;
     const int x = (int)(blockIdx.x % kXcds), w = (int)(blockIdx.x / kXcds);
@@ -713,8 +759,14 @@ inline int pick_cfg(int64_t q, int cols, int cost, int forced_nq) {
     return best;
 }
 
+// Entry chunks: chunk_blocks if given, else about target_items items.  With
+// `slots` (the launch's resident work-groups, a multiple of 8) the chunk count
+// is chosen so the items fill whole rounds of the persistent grid: n_items <=
+// rounds * slots, so no work-group runs a round more than the others (the
+// XCD ranges hold at most rounds * slots / 8 items each).  min_chunks raises
+// the chunk count where a caller needs that many partials per query.
 inline Plan make_plan(int64_t n, int64_t q, int cfg, int chunk_blocks, int rows, int cols,
-                      int64_t target_items = 8192) {
+                      int64_t target_items = 8192, int64_t slots = 0, int64_t min_chunks = 1) {
     Plan p;
     p.nq = kCfgNQ[cfg];
     p.wq = kCfgWQ[cfg];
@@ -724,12 +776,22 @@ inline Plan make_plan(int64_t n, int64_t q, int cfg, int chunk_blocks, int rows,
     p.n_qb = (int32_t)((q + qb - 1) / qb);
     p.q_pad = (int64_t)p.n_qb * qb;
     p.n_blocks = (int32_t)((n + rows - 1) / rows);
-    if (chunk_blocks <= 0) {
+    if (chunk_blocks <= 0 && slots >= kXcds) {
+        const int64_t max_chunks = std::max<int64_t>(1, p.n_blocks / 8);
+        const int64_t rounds = std::max<int64_t>(1, (target_items + slots / 2) / slots);
+        int64_t want = std::max<int64_t>(1, rounds * slots / p.n_qb);
+        want = std::min(std::max(want, min_chunks), max_chunks);
+        chunk_blocks = (int32_t)((p.n_blocks + want - 1) / want);
+    } else if (chunk_blocks <= 0) {
         int64_t want_chunks = std::max<int64_t>(1, (target_items + p.n_qb - 1) / p.n_qb);
+        want_chunks = std::max(want_chunks, min_chunks);
         chunk_blocks =
             (int32_t)std::max<int64_t>(8, (p.n_blocks + want_chunks - 1) / want_chunks);
     }
-    p.chunk_blocks = std::min<int32_t>(chunk_blocks, p.n_blocks);
+    // a chunk is addressed through one buffer descriptor: below 2^31 bytes
+    // for rows of up to 128 float32 values
+    const int32_t max_chunk = (int32_t)(((int64_t)1 << 31) / ((int64_t)rows * 512)) - 1;
+    p.chunk_blocks = std::min<int32_t>(std::min(chunk_blocks, max_chunk), p.n_blocks);
     p.n_chunks = (p.n_blocks + p.chunk_blocks - 1) / p.chunk_blocks;
     p.n_items = p.n_qb * p.n_chunks;
     return p;
@@ -819,6 +881,40 @@ inline int launch_tile(int mode, int cfg, const Plan &p, const ScanArgs &A, hipS
     return 1;
 }
 
+// Resident work-groups of the kernel a launch_tile call with the same mode and
+// configuration would start (its persistent grid for an unbounded item count);
+// 0 if not compiled.
+template <class Tile, int MODE, int C>
+inline unsigned slots_one() {
+    if constexpr (kCfgNQ[C] * tile_cost<Tile>() <= kTileBudget)
+        return persistent_grid<Tile, kCfgNQ[C], kCfgWQ[C], MODE>(1 << 30);
+    return 0;
+}
+template <class Tile, int MODE>
+inline unsigned slots_cfgs(int cfg) {
+    switch (cfg) {
+        case 0: return slots_one<Tile, MODE, 0>();
+        case 1: return slots_one<Tile, MODE, 1>();
+        case 2: return slots_one<Tile, MODE, 2>();
+        case 3: return slots_one<Tile, MODE, 3>();
+        case 4: return slots_one<Tile, MODE, 4>();
+        case 5: return slots_one<Tile, MODE, 5>();
+    }
+    return 0;
+}
+template <class Tile, bool Window>
+inline unsigned tile_slots(int mode, int cfg) {
+    if (cfg < 0 || cfg >= kNumCfg) return 0;
+    switch (mode) {
+        case kArgmax: return slots_cfgs<Tile, kArgmax>(cfg);
+        case kFilter: return slots_cfgs<Tile, kFilter>(cfg);
+        case kWindow:
+            if constexpr (Window) return slots_cfgs<Tile, kWindow>(cfg);
+            return 0;
+    }
+    return 0;
+}
+
 // Several databases in one launch (argmax and filter modes).  The grid is
 // sized by the occupancy of the single-database kernel of the same tile.
 template <class Tile, int MODE, int C>
@@ -887,6 +983,13 @@ int launch_scan_fp8(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
                     hipStream_t s);         // widths 16, 32 (32x32)
 int launch_scan_int8(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
                      hipStream_t s);        // widths 16, 32 (32x32)
+// Resident work-groups of the scan kernel of (mode, width, configuration), 0
+// if not compiled: one function per launcher above.
+unsigned slots_scan_f32_narrow(int mode, int w, int cfg);
+unsigned slots_scan_f32_wide(int mode, int w, int cfg);
+unsigned slots_scan_bf16(int mode, int w, int cfg);
+unsigned slots_scan_fp8(int mode, int w, int cfg);
+unsigned slots_scan_int8(int mode, int w, int cfg);
 // Several databases of one stream width in one launch: float32 widths 8, 16,
 // 32; bf16 and fp8 widths 16, 32.  Nonzero if not compiled.
 int launch_scan_multi(int precision, int mode, int w, int cfg, const ScanArgs *dbs,

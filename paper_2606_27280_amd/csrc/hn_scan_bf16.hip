@@ -12,4 +12,13 @@ int launch_scan_bf16(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
     }
     return 1;
 }
+unsigned slots_scan_bf16(int mode, int w, int cfg) {
+    switch (w) {
+        case 16: return tile_slots<BF16Tile32<16>, true>(mode, cfg);
+        case 32: return tile_slots<BF16Tile32<32>, true>(mode, cfg);
+        case 64: return tile_slots<BF16Tile<64>, true>(mode, cfg);
+        case 128: return tile_slots<BF16Tile<128>, true>(mode, cfg);
+    }
+    return 0;
+}
 }  // namespace hn

@@ -13,4 +13,13 @@ int launch_scan_f32_narrow(int mode, int w, int cfg, const Plan &p, const ScanAr
     }
     return 1;
 }
+unsigned slots_scan_f32_narrow(int mode, int w, int cfg) {
+    switch (w) {
+        case 4: return tile_slots<F32Tile32<4>, true>(mode, cfg);
+        case 8: return tile_slots<F32Tile32<8>, true>(mode, cfg);
+        case 16: return tile_slots<F32Tile32<16>, true>(mode, cfg);
+        case 32: return tile_slots<F32Tile32<32>, true>(mode, cfg);
+    }
+    return 0;
+}
 }  // namespace hn

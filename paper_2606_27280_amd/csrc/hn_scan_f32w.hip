@@ -11,4 +11,11 @@ int launch_scan_f32_wide(int mode, int w, int cfg, const Plan &p, const ScanArgs
     }
     return 1;
 }
+unsigned slots_scan_f32_wide(int mode, int w, int cfg) {
+    switch (w) {
+        case 64: return tile_slots<F32Tile<64>, true>(mode, cfg);
+        case 128: return tile_slots<F32Tile<128>, true>(mode, cfg);
+    }
+    return 0;
+}
 }  // namespace hn

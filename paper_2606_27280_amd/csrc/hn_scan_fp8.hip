@@ -10,4 +10,11 @@ int launch_scan_fp8(int mode, int w, int cfg, const Plan &p, const ScanArgs &A, 
     }
     return 1;
 }
+unsigned slots_scan_fp8(int mode, int w, int cfg) {
+    switch (w) {
+        case 16: return tile_slots<FP8Tile32<16>, true>(mode, cfg);
+        case 32: return tile_slots<FP8Tile32<32>, true>(mode, cfg);
+    }
+    return 0;
+}
 }  // namespace hn

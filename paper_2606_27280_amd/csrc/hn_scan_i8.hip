@@ -9,4 +9,11 @@ int launch_scan_int8(int mode, int w, int cfg, const Plan &p, const ScanArgs &A,
     }
     return 1;
 }
+unsigned slots_scan_int8(int mode, int w, int cfg) {
+    switch (w) {
+        case 16: return tile_slots<I8Tile32<16>, true>(mode, cfg);
+        case 32: return tile_slots<I8Tile32<32>, true>(mode, cfg);
+    }
+    return 0;
+}
 }  // namespace hn

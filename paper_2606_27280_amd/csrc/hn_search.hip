@@ -105,7 +105,8 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     if (W.cfg < 0)
         return fail(HN_ERR_INVALID_ARG, "query_tiles=%d is not available for this width",
                     o.query_tiles);
-    W.plan = make_plan(ix->n, q, W.cfg, o.chunk_blocks, ti.rows, ti.cols);
+    W.plan = make_plan(ix->n, q, W.cfg, o.chunk_blocks, ti.rows, ti.cols, 8192,
+                       scan_slots(W.precision, window ? kWindow : kFilter, W.width, W.cfg));
     const Plan &p = W.plan;
     // The argmax (seed) scan runs on the bf16 copy whatever the filter's
     // precision: the seed only has to be a real entry with a near-maximal
@@ -116,11 +117,10 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     if (W.seed_cfg < 0)
         return fail(HN_ERR_INVALID_ARG, "query_tiles=%d is not available for this width",
                     o.query_tiles);
-    W.seed_plan = make_plan(ix->n, q, W.seed_cfg, o.chunk_blocks, tis.rows, tis.cols);
     // top-k seeds take the best of up to 2 topk chunks: plan at least that many
-    if (topk > 1 && o.chunk_blocks == 0 && W.seed_plan.n_chunks < 2 * topk)
-        W.seed_plan = make_plan(ix->n, q, W.seed_cfg, 0, tis.rows, tis.cols,
-                                (int64_t)W.seed_plan.n_qb * 2 * topk);
+    W.seed_plan = make_plan(ix->n, q, W.seed_cfg, o.chunk_blocks, tis.rows, tis.cols, 8192,
+                            scan_slots(HN_PREC_BF16, kArgmax, ix->kb, W.seed_cfg),
+                            topk > 1 ? 2 * (int64_t)topk : 1);
     W.shape = tis.rows;
     const Plan &sp = W.seed_plan;
     const int64_t qp = std::max(p.q_pad, sp.q_pad);
@@ -787,7 +787,8 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     hipStream_t s = (hipStream_t)stream;
     const TileInfo ti = tile_info(HN_PREC_FP32, kDim);
     const int cfg = pick_cfg(q, ti.cols, ti.cost, 2);
-    Plan p = make_plan(n, q, cfg, 0, ti.rows, ti.cols);
+    Plan p = make_plan(n, q, cfg, 0, ti.rows, ti.cols, 8192,
+                       scan_slots(HN_PREC_FP32, kWindow, kDim, cfg));
     // A prefix pass (one chunk of the first n_pre rows) gives each query a
     // starting running maximum: a real scan score, so never above the final
     // maximum, and far fewer near-record candidates in the main pass.
