@@ -364,14 +364,16 @@ __device__ __forceinline__ void flush_pairs(const ScanArgs &A, EmitBuf &B) {
 
 // Append the lane's entries with score >= t, in groups of 4 accumulator
 // slots: ballot per slot, positions by popcount + mbcnt prefix counts.  Rows
-// past the database end are never appended (their scores are -inf, which a
-// threshold of -inf would otherwise accept).
+// past the database end are never appended: the scan sets their scores to
+// NaN, which compares false with every threshold (-inf included).
+// Padding queries never pass: the caller's threshold for them is +inf (or a
+// window limit of +inf / NaN), so the slot test is one comparison, whose lane
+// mask is the ballot itself.
 template <class Tile, bool WithVal, bool Direct>
 __device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B,
-                                           const typename Tile::Acc &a, float t, bool qvalid,
-                                           int q, int eblk) {
+                                           const typename Tile::Acc &a, float t, int q,
+                                           int eblk) {
     const int lane = (int)__lane_id();
-    const int rows_left = (int)min<int64_t>(A.n - eblk, (int64_t)Tile::kRows);
 #pragma unroll
     for (int v0 = 0; v0 < Tile::kAcc; v0 += 4) {
         bool pv[4];
@@ -380,7 +382,7 @@ __device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B,
         int total = 0;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            pv[u] = qvalid && a[v0 + u] >= t && Tile::out_row(lane, v0 + u) < rows_left;
+            pv[u] = a[v0 + u] >= t;
             mv[u] = __ballot(pv[u]);
             c[u] = __popcll(mv[u]);
             total += c[u];
@@ -451,7 +453,11 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
             Tile::load_q(qf[t], qsrc + (int64_t)qid[t] * A.q_stride + g * Tile::kSlice);
         else
             Tile::zero_q(qf[t]);
-        thr[t] = (MODE == kFilter || MODE == kWindow) ? A.thr[qid[t]] : 0.0f;
+        // padding queries: a filter threshold of +inf, a window threshold of
+        // -inf (limit best + inf): neither ever passes
+        thr[t] = MODE == kFilter   ? (qid[t] < A.q_count ? A.thr[qid[t]] : INFINITY)
+                 : MODE == kWindow ? (qid[t] < A.q_count ? A.thr[qid[t]] : -INFINITY)
+                                   : 0.0f;
         best[t] = (MODE == kWindow && A.init_best) ? A.init_best[qid[t]] : -INFINITY;
         bblk[t] = -1;
     }
@@ -474,7 +480,10 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
     // computed the other one is loading.  Every slot is loaded on every step
     // (past the item's end the address is clamped to its last block), so the
     // loads in flight at any point are a fixed, whole group.
-    constexpr int PF = Tile::kFragRegs <= 2 ? 8 : (Tile::kFragRegs <= 4 ? 4 : 1);
+#ifndef HN_PF_WIDE
+#define HN_PF_WIDE 1
+#endif
+    constexpr int PF = Tile::kFragRegs <= 2 ? 8 : (Tile::kFragRegs <= 4 ? 4 : HN_PF_WIDE);
     const int blk_last = max(blk1 - 1, 0);
     auto load_group = [&](Frag (&xg)[PF], int gbase) {
 #pragma unroll
@@ -497,7 +506,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
                 for (int t = 0; t < NQ; ++t)
 #pragma unroll
                     for (int v = 0; v < NA; ++v)
-                        if (eblk + Tile::out_row(lane, v) >= A.n) acc[t][v] = -INFINITY;
+                        if (eblk + Tile::out_row(lane, v) >= A.n) acc[t][v] = __builtin_nanf("");
             }
             float mx[NQ];
 #pragma unroll
@@ -518,8 +527,8 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
 #pragma unroll
                     for (int t = 0; t < NQ; ++t)
                         if (__ballot(mx[t] >= thr[t]))
-                            emit_pairs<Tile, false, Direct>(A, eb, acc[t], thr[t],
-                                                            qid[t] < A.q_count, qid[t], eblk);
+                            emit_pairs<Tile, false, Direct>(A, eb, acc[t], thr[t], qid[t],
+                                                            eblk);
                 }
             } else if constexpr (MODE == kWindow) {
                 float lim[NQ];
@@ -534,8 +543,8 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
 #pragma unroll
                     for (int t = 0; t < NQ; ++t)
                         if (__ballot(mx[t] >= lim[t]))
-                            emit_pairs<Tile, true, Direct>(A, eb, acc[t], lim[t],
-                                                           qid[t] < A.q_count, qid[t], eblk);
+                            emit_pairs<Tile, true, Direct>(A, eb, acc[t], lim[t], qid[t],
+                                                           eblk);
                 }
             } else {
 #pragma unroll
