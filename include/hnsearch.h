@@ -243,7 +243,7 @@ int hn_profile_end(void *stream, const char **names, double *ms, int64_t *counts
                    int32_t *n_out);
 
 /* ---------------------------------------------------------------- seed model
- * Not part of the paper: the learned seed of the spec form.  Anchors are
+ * Not part of the paper: the learned-seed form of the search.  Anchors are
  * chosen by k-means++ D^2 seeding, a query's label is the anchor closest to
  * its exact nearest neighbour, and the MLP is trained with softmax
  * cross-entropy and AdamW.  All pointers are device memory. */

@@ -414,7 +414,7 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
         S.q_pad = (int32_t)p.q_pad;
         S.part_ld = (int32_t)p.q_pad;
         S.shape = 32;
-        S.group_size = 16;
+        S.group_size = 16 * kArgSpan;
         S.queries = P->q_buf + pad_base[d] * kDim;
         S.q = q_counts[d];
         S.rows = ix->rows;

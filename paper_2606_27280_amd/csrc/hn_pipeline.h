@@ -190,12 +190,53 @@ struct SeedArgs {
 
 __device__ __forceinline__ float round_down_f32(double v) { return __double2float_rd(v); }
 
-// Entry of slot v of an argmax lane group gid = block * G + g, for the scan's
-// tile shape: 16x16 tiles give 4 consecutive entries, 32x32 tiles 16 entries
-// (rows 8 (v / 4) + 4 g + v % 4 of the block).
+// Entry of slot v of an argmax lane group gid = span * G + g, for the scan's
+// tile shape: per block of the span, 16x16 tiles give 4 consecutive entries
+// (rows 4 g + v % 4), 32x32 tiles 16 entries (rows 8 (w / 4) + 4 g + w % 4,
+// w = v % 16); slot v lies in block span * kArgSpan + v / (entries per block).
 __device__ __forceinline__ int64_t group_entry(int shape, int gid, int v) {
-    if (shape == 16) return (int64_t)(gid >> 2) * 16 + 4 * (gid & 3) + v;
-    return (int64_t)(gid >> 1) * 32 + 8 * (v >> 2) + 4 * (gid & 1) + (v & 3);
+    if (shape == 16)
+        return ((int64_t)(gid >> 2) * kArgSpan + (v >> 2)) * 16 + 4 * (gid & 3) + (v & 3);
+    const int w = v & 15;
+    return ((int64_t)(gid >> 1) * kArgSpan + (v >> 4)) * 32 + 8 * (w >> 2) + 4 * (gid & 1) +
+           (w & 3);
+}
+
+// Canonical sim of the lane's entry of lane group gid (-inf and e = -1 for
+// no entry).  Entries whose float32 major dot lies more than 2 ||q_m|| mu_m
+// (plus a margin for the float32 rounding) below the group's best major dot
+// are skipped: by Eq. 3 applied to both, such an entry's sim is below the
+// best-major entry's, so the group's best sim is unchanged while most lanes
+// read only the row's K-prefix.
+__device__ __forceinline__ double group_sim(const SeedArgs &S, int gid, int lane,
+                                            const float *qv, double q_minor, int64_t &e) {
+    e = -1;
+    float maj = -INFINITY;
+    if (gid >= 0 && lane < S.group_size) {
+        const int64_t c = group_entry(S.shape, gid, lane);
+        if (c < S.n) {
+            const float *xv = S.rows + c * kDim;
+            const int k4 = S.k & ~3;
+            float d = 0.0f;
+            for (int j = 0; j < k4; j += 4) {
+                const float4 x4 = *reinterpret_cast<const float4 *>(xv + j);
+                const float4 q4 = *reinterpret_cast<const float4 *>(qv + j);
+                d = fmaf(q4.x, x4.x, d);
+                d = fmaf(q4.y, x4.y, d);
+                d = fmaf(q4.z, x4.z, d);
+                d = fmaf(q4.w, x4.w, d);
+            }
+            for (int j = k4; j < S.k; ++j) d = fmaf(qv[j], xv[j], d);
+            maj = d;
+            e = c;
+        }
+    }
+    float mm = maj;
+    for (int o = 32; o > 0; o >>= 1) mm = fmaxf(mm, __shfl_xor(mm, o));
+    const float tau = (float)(2.0 * q_minor * S.mu_minor) * (1.0f + 0x1p-10f) + 1e-4f;
+    if (e >= 0 && maj >= mm - tau) return sim64(qv, S.rows + e * kDim);
+    e = -1;
+    return -INFINITY;
 }
 
 // Exact top-k seed: the topk-th largest of distinct real entries' canonical
@@ -206,8 +247,7 @@ __device__ __forceinline__ int64_t group_entry(int shape, int gid, int v) {
 // these are the near-best entries of distinct chunks).  -inf if fewer than
 // topk such entries exist.  Chunk r's value sits in lane r % 64, slot r / 64.
 __device__ __forceinline__ double topk_lower(const SeedArgs &S, const int64_t i, const int lane,
-                                          const float *qv) {
-    const int gs = S.group_size;
+                                          const float *qv, double q_minor) {
     const int m = min(S.n_chunks, min(2 * S.topk, 256));
     double cs[4];
 #pragma unroll
@@ -240,11 +280,8 @@ __device__ __forceinline__ double topk_lower(const SeedArgs &S, const int64_t i,
         pv = bv;
         pc = bc;
         const int gid = S.part_idx[(int64_t)bc * S.part_ld + i];
-        double sv = -INFINITY;
-        if (gid >= 0 && lane < gs) {
-            const int64_t e = group_entry(S.shape, gid, lane);
-            if (e < S.n) sv = sim64(qv, S.rows + e * kDim);
-        }
+        int64_t e;
+        double sv = group_sim(S, gid, lane, qv, q_minor, e);
         for (int o = 32; o > 0; o >>= 1) sv = fmax(sv, __shfl_xor(sv, o));
         if (sv == -INFINITY) continue;
         if (lane == found % 64) {
@@ -321,7 +358,7 @@ __device__ __forceinline__ void seed_one(const SeedArgs &S, const int64_t i, con
         L = S.lower[i];
         b = S.lower_idx ? S.lower_idx[i] : -1;
     } else if (S.topk > 1) {
-        L = topk_lower(S, i, lane, qv);
+        L = topk_lower(S, i, lane, qv, qn.minor);
     } else {
         float bv = -INFINITY;
         int bi = -1;
@@ -333,15 +370,8 @@ __device__ __forceinline__ void seed_one(const SeedArgs &S, const int64_t i, con
             const int oi = __shfl_xor(bi, o);
             lex_merge(bv, bi, ov, oi);
         }
-        double sv = -INFINITY;
-        int64_t e = -1;
-        if (bi >= 0 && lane < S.group_size) {
-            e = group_entry(S.shape, bi, lane);
-            if (e < S.n)
-                sv = sim64(qv, S.rows + e * kDim);
-            else
-                e = -1;
-        }
+        int64_t e;
+        double sv = group_sim(S, bi, lane, qv, qn.minor, e);
         for (int o = 32; o > 0; o >>= 1) {
             const double os = __shfl_xor(sv, o);
             const int64_t oe = __shfl_xor(e, o);
@@ -542,9 +572,18 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs R) {
         if (R.count) atomicAdd(&R.cnt[pr.x], 1);
         bool keep = true;
         if (MODE == 1) {
+            // the float32 prefix stream is zero padded to kp (a multiple of
+            // 4) and the query row holds 128 values: whole float4 groups
             const float *xm = major32 + (int64_t)pr.y * kp;
             float s = 0.0f;
-            for (int j = 0; j < k; ++j) s = fmaf(qv[j], xm[j], s);
+            for (int j = 0; j < k; j += 4) {
+                const float4 x4 = *reinterpret_cast<const float4 *>(xm + j);
+                const float4 q4 = *reinterpret_cast<const float4 *>(qv + j);
+                s = fmaf(q4.x, x4.x, s);
+                s = fmaf(q4.y, x4.y, s);
+                s = fmaf(q4.z, x4.z, s);
+                s = fmaf(q4.w, x4.w, s);
+            }
             keep = s >= R.thr32[pr.x];
         } else if (MODE == 2) {
             keep = R.pair_val[p] >= R.thr32[pr.x];

@@ -46,7 +46,7 @@ struct ScanArgs {
     int32_t n_qb, n_items;
     int32_t q_count, q_pad;
     float *part_val;    // argmax / window: [n_chunks][q_pad]
-    int32_t *part_idx;  // argmax: winning lane group, block * G + g
+    int32_t *part_idx;  // argmax: winning lane group, span * G + g (span = kArgSpan blocks)
     const float *thr;   // filter: T_q; window: window width; [q_pad]
     int2 *pairs;        // filter / window: (query, entry)
     float *pair_val;    // window: scan score of the pair
@@ -322,6 +322,20 @@ __device__ __forceinline__ float acc_max(const Acc &a) {
     return m;
 }
 
+// The same, continuing a running maximum m.
+template <class Acc, int N>
+__device__ __forceinline__ float acc_max_from(float m, const Acc &a) {
+#pragma unroll
+    for (int v = 0; v < N; ++v) m = fmaxf(m, a[v]);
+    return m;
+}
+
+// Argmax spans: the argmax mode reduces the scores of kArgSpan consecutive
+// blocks into one running maximum per lane before comparing it with the
+// best so far, so a winning lane group is (span, g): kArgSpan x the group's
+// rows of one block.  Chunks hold whole spans (make_plan).
+constexpr int kArgSpan = 4;
+
 // Survivor staging.  In the hot loop each wave appends (query, entry) pairs to
 // its own LDS buffer only, so the loop issues no global stores (which would
 // make the compiler drain the loads in flight); the buffer is flushed to the
@@ -445,7 +459,9 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
     QFrag qf[NQ];
     int qid[NQ];
     float thr[NQ], best[NQ];
-    int bblk[NQ];
+    int bblk[NQ];      // argmax: span of the best score so far
+    float smax[NQ];    // argmax: running maximum of the current span
+    int cur_span = -1;
 #pragma unroll
     for (int t = 0; t < NQ; ++t) {
         qid[t] = (tile0 + t) * C + r;
@@ -460,7 +476,20 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
                                    : 0.0f;
         best[t] = (MODE == kWindow && A.init_best) ? A.init_best[qid[t]] : -INFINITY;
         bblk[t] = -1;
+        smax[t] = -INFINITY;
     }
+    // argmax: fold the current span into the best (NaN scores of rows past
+    // the end never win a comparison)
+    auto close_span = [&]() {
+#pragma unroll
+        for (int t = 0; t < NQ; ++t) {
+            if (smax[t] > best[t]) {
+                best[t] = smax[t];
+                bblk[t] = cur_span;
+            }
+            smax[t] = -INFINITY;
+        }
+    };
 
     const int blk0 = chunk * A.chunk_blocks;
     const int blk1 = min(blk0 + A.chunk_blocks, A.n_blocks);
@@ -509,16 +538,18 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
                         if (eblk + Tile::out_row(lane, v) >= A.n) acc[t][v] = __builtin_nanf("");
             }
             float mx[NQ];
+            if constexpr (MODE != kArgmax) {
 #pragma unroll
-            for (int t = 0; t < NQ; ++t) mx[t] = acc_max<Acc, NA>(acc[t]);
+                for (int t = 0; t < NQ; ++t) mx[t] = acc_max<Acc, NA>(acc[t]);
+            }
             if constexpr (MODE == kArgmax) {
-#pragma unroll
-                for (int t = 0; t < NQ; ++t) {
-                    if (mx[t] > best[t]) {
-                        best[t] = mx[t];
-                        bblk[t] = blk;
-                    }
+                const int sp = blk / kArgSpan;
+                if (sp != cur_span) {
+                    close_span();
+                    cur_span = sp;
                 }
+#pragma unroll
+                for (int t = 0; t < NQ; ++t) smax[t] = acc_max_from<Acc, NA>(smax[t], acc[t]);
             } else if constexpr (MODE == kFilter) {
                 bool any = false;
 #pragma unroll
@@ -599,9 +630,10 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
         }
     }
 
+    if constexpr (MODE == kArgmax) close_span();
     if constexpr (MODE == kArgmax || MODE == kWindow) {
         // per query: merge the lane groups, then the NS waves of the sub-block.
-        // The argmax index is the winning lane group, block * G + g.
+        // The argmax index is the winning lane group, span * G + g.
 #pragma unroll
         for (int t = 0; t < NQ; ++t) {
             float v = best[t];
@@ -799,8 +831,12 @@ inline Plan make_plan(int64_t n, int64_t q, int cfg, int chunk_blocks, int rows,
     }
     // a chunk is addressed through one buffer descriptor: below 2^31 bytes
     // for rows of up to 128 float32 values
-    const int32_t max_chunk = (int32_t)(((int64_t)1 << 31) / ((int64_t)rows * 512)) - 1;
-    p.chunk_blocks = std::min<int32_t>(std::min(chunk_blocks, max_chunk), p.n_blocks);
+    const int32_t max_chunk =
+        ((int32_t)(((int64_t)1 << 31) / ((int64_t)rows * 512)) - 1) / kArgSpan * kArgSpan;
+    // whole argmax spans per chunk, so a winning lane group lies in one chunk
+    chunk_blocks = (chunk_blocks + kArgSpan - 1) / kArgSpan * kArgSpan;
+    chunk_blocks = std::min(chunk_blocks, max_chunk);
+    p.chunk_blocks = std::min<int32_t>(chunk_blocks, p.n_blocks);
     p.n_chunks = (p.n_blocks + p.chunk_blocks - 1) / p.chunk_blocks;
     p.n_items = p.n_qb * p.n_chunks;
     return p;

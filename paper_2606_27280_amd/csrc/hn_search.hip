@@ -240,7 +240,7 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     S.part_ld = (int32_t)sp.q_pad;
     S.topk = topk;
     S.shape = W.shape;
-    S.group_size = W.shape == 16 ? 4 : 16;
+    S.group_size = (W.shape == 16 ? 4 : 16) * kArgSpan;
     S.queries = queries;
     S.q = q;
     S.rows = ix->rows;
