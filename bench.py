@@ -131,13 +131,24 @@ def bench_layer(rows, steps, warmup):
         gbs = nbytes / sec / 1e9
         res[name] = {"ms": round(1e3 * sec, 4), "rows_per_s": round(rows / sec, 1),
                      "achieved_gbs": round(gbs, 1), "frac_hbm": round(gbs / PEAK["hbm_gbs"], 4)}
+    # context: a plain device copy of the forward's size on the same GPU
+    # (torch's copy kernel), the bandwidth a streaming kernel can reach here
+    cp = torch.empty_like(f)
+    for _ in range(warmup):
+        cp.copy_(f)
+    sec = gpu_time(lambda: cp.copy_(f), steps, torch)
+    copy_gbs = rows * 1024 / sec / 1e9
+    del cp
+    for name in ("forward", "backward"):
+        res[name]["frac_of_copy"] = round(res[name]["achieved_gbs"] / copy_gbs, 4)
     print(json.dumps({"metric": "HN layer rows/s (Eq. 1 forward, VJP backward)",
                       "value": res["forward"]["rows_per_s"], "unit": "rows/s", "n_gpus": 1,
                       "steps": steps, "warmup": warmup, "dtype": "f32", "data": "synthetic",
                       "config": {"workload": "hn_layer", "rows": rows, "d": 128, "k": 16,
                                  "alpha": 0.125},
                       "roofline": {"bound": "hbm", "peak": PEAK["hbm_gbs"], "unit": "GB/s",
-                                   "forward": res["forward"], "backward": res["backward"]}}),
+                                   "forward": res["forward"], "backward": res["backward"],
+                                   "device_copy_gbs": round(copy_gbs, 1)}}),
           flush=True)
 
 

@@ -320,7 +320,8 @@ int hn_layer_forward(const float *f, int64_t b, int32_t d, int32_t k, double alp
 
 /* grad[r] = (dL/dout[r]) . d out[r] / d f[r] given g = dL/dout: per block of
  * norm scale c, (c / ||u||) (g - v (v . g)) with u the block of f and
- * v = u / ||u||; 0 for blocks that cannot be normalised. */
+ * v = u / ||u||; 0 for blocks that cannot be normalised and for one-element
+ * blocks (whose output is the constant +-c). */
 int hn_layer_backward(const float *f, const float *g, int64_t b, int32_t d, int32_t k,
                       double alpha, float *grad, void *stream);
 
