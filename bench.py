@@ -69,6 +69,10 @@ def parse():
                     help="skip timing the other scan precisions")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--query-tiles", type=int, default=0)
+    ap.add_argument("--queries", type=int, default=0,
+                    help="queries of the streaming workload (--workload 6; default 32)")
+    ap.add_argument("--table3", action="store_true",
+                    help="the (K, alpha) grid of the paper's Table 3 at N = 500,000")
     ap.add_argument("--chunk-blocks", type=int, default=0)
     ap.add_argument("--seed", default=None, choices=["plain", "learned", "window"],
                     help="timed seed form (default: learned for workload 5, else plain)")
@@ -152,6 +156,153 @@ def bench_layer(rows, steps, warmup):
           flush=True)
 
 
+def device_copy_gbs(nbytes, steps, torch):
+    """Read + write bandwidth of torch's device copy of nbytes (a streaming
+    kernel's practical ceiling on this GPU)."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    sec = gpu_time(lambda: b.copy_(a), steps, torch)
+    return 2 * nbytes / sec / 1e9
+
+
+def bench_stream(args):
+    """Small-Q regime: 32 queries (one query tile) against N = 2^24 entries,
+    K = 16, alpha = 1/8, 65,536 clusters, so that every scan pass streams its
+    whole K-prefix copy (float32: 1 GiB, bf16: 512 MiB, both larger than the
+    256 MB Infinity Cache) from HBM.  Inputs are drawn on the device (torch's
+    Philox generator, seed 0x484E0006) with the recipe of the other workloads
+    and placed on the HN sphere by the library's HN layer."""
+    import torch
+
+    import paper_2606_27280_amd as hn
+    from paper_2606_27280_amd import accounting as acc
+    n, k, alpha, nc, q = 1 << 24, 16, 0.125, 1 << 16, args.queries or 32
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(0x484E0006)
+    log("generating hn_n16m_k16_stream on the device (N=%d, K=%d, Q=%d)" % (n, k, q))
+    centres = torch.randn((nc, 128), generator=g, device=dev)
+    ids = torch.randint(0, nc, (n,), generator=g, device=dev)
+    raw = centres[ids]
+    raw.add_(torch.randn((n, 128), generator=g, device=dev), alpha=0.3)
+    db = hn.hn_layer(raw, k, alpha)
+    del raw, centres, ids
+    r = torch.randint(0, n, (q,), generator=g, device=dev)
+    qs = hn.hn_layer(db[r] + 0.05 * torch.randn((q, 128), generator=g, device=dev), k, alpha)
+    torch.cuda.synchronize()
+    log("building index")
+    ix = hn.Index(db, k, alpha)
+    idx = torch.empty(q, dtype=torch.int64, device=dev)
+    sim = torch.empty(q, dtype=torch.float64, device=dev)
+    elem = {"f32": 4, "bf16": 2, "fp8": 1, "int8": 1}
+    forms = {}
+    for prec in ("fp32", "bf16", "int8"):
+        def step():
+            ix.search(qs, out=(idx, sim), precision=prec)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        with hn.profile() as prof:
+            sec, _ = timed(step, args.steps, 0, torch)
+        passes = {}
+        for kname, v in prof.result.items():
+            if kname.startswith("scan_"):
+                t = v["ms"] / v["launches"] / 1e3
+                sb = n * k * elem[kname.rsplit("_", 1)[1]]
+                passes[kname] = {"avg_ms": round(1e3 * t, 4), "stream_bytes": sb,
+                                 "stream_gbs": round(sb / t / 1e9, 1),
+                                 "frac_hbm": round(sb / t / 1e9 / PEAK["hbm_gbs"], 4)}
+        forms[prec] = {"queries_per_s": round(q * args.steps / sec, 1),
+                       "ms_per_step": round(1e3 * sec / args.steps, 4), "passes": passes}
+        log("%s: %s" % (prec, forms[prec]))
+    ix.search(qs, out=(idx, sim), precision="fp32")
+    bidx = torch.empty(q, dtype=torch.int64, device=dev)
+    bsim = torch.empty(q, dtype=torch.float64, device=dev)
+
+    def bf_step():
+        hn.bruteforce_top1(db, qs, out=(bidx, bsim))
+    bf_step()
+    torch.cuda.synchronize()
+    bsec, _ = timed(bf_step, max(1, args.bf_steps), 0, torch)
+    bqps = q * max(1, args.bf_steps) / bsec
+    exact = bool(torch.equal(bidx, idx) and torch.equal(bsim, sim))
+    copy = device_copy_gbs(1 << 30, 10, torch)
+    main_pass = forms["fp32"]["passes"].get("scan_filter_f32", {})
+    print(json.dumps({
+        "metric": "exact top-1 queries/s, small-Q regime (each scan pass streams its K-prefix "
+                  "copy from HBM)",
+        "value": forms["fp32"]["queries_per_s"], "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "hn_n16m_k16_stream", "n": n, "d": 128, "k": k, "alpha": alpha,
+                   "queries": q, "clusters": nc, "seed": "plain", "rescoring": "f64"},
+        "roofline": {"bound": "hbm", "kernel": "scan_filter_f32",
+                     "achieved": main_pass.get("stream_gbs"), "peak": PEAK["hbm_gbs"],
+                     "unit": "GB/s", "frac": main_pass.get("frac_hbm"),
+                     "device_copy_gbs": round(copy, 1)},
+        "forms": forms,
+        "bruteforce": {"queries_per_s": round(bqps, 1),
+                       "ms_per_step": round(1e3 * bsec / max(1, args.bf_steps), 3),
+                       "stream_gbs": round(n * 512 / (bsec / max(1, args.bf_steps)) / 1e9, 1)},
+        "speedup_vs_bruteforce": round(forms["fp32"]["queries_per_s"] / bqps, 2),
+        "exact_vs_bruteforce": exact}), flush=True)
+    ix.close()
+
+
+# Table 3 of the paper (trevi, N = 500,000): speed-up of HN over the CPU
+# brute-force scan and the fraction of entries evaluated in full, per (K,
+# alpha).  Another machine's figures, shown beside this GPU's for context.
+PAPER_TABLE3 = {(16, 0.0): (8.8, 0.0), (16, 1 / 32): (7.8, 0.4), (16, 1 / 16): (8.0, 0.6),
+                (16, 1 / 8): (7.2, 1.2), (16, 1 / 4): (4.0, 5.5), (8, 0.0): (18.0, 0.0),
+                (8, 1 / 32): (13.7, 0.4), (8, 1 / 16): (12.7, 0.6), (8, 1 / 8): (10.1, 1.5),
+                (8, 1 / 4): (4.3, 6.6)}
+
+
+def bench_table3(args):
+    """The (K, alpha) grid of Table 3 at the paper's size: N = 500,000 (1,953
+    clusters, about 256 entries each), 200 perturbed queries, fp32 HN search
+    and the GPU brute force on the same queries."""
+    import torch
+
+    import hn_inputs
+    import paper_2606_27280_amd as hn
+    dev = torch.device("cuda:0")
+    n, nc, q = 500000, 1953, 200
+    rows = []
+    for (k, alpha), (p_speed, p_ph2) in PAPER_TABLE3.items():
+        seed = hn_inputs.DB_SEED_BASE + 0x30 + 2 * k + int(round(alpha * 32))
+        db = hn_inputs.make_db(n, k, alpha, nc, seed)
+        qs = hn_inputs.make_queries(db, k, alpha, q, 0, seed + hn_inputs.QUERY_SEED_OFFSET)
+        d_db, d_q = torch.from_numpy(db).to(dev), torch.from_numpy(qs).to(dev)
+        ix = hn.Index(d_db, k, alpha)
+        idx = torch.empty(q, dtype=torch.int64, device=dev)
+        sim = torch.empty(q, dtype=torch.float64, device=dev)
+        sec, _ = timed(lambda: ix.search(d_q, out=(idx, sim)), args.steps, args.warmup, torch)
+        _, _, aux = ix.search(d_q, aux=True)
+        bidx = torch.empty(q, dtype=torch.int64, device=dev)
+        bsim = torch.empty(q, dtype=torch.float64, device=dev)
+        bsec, _ = timed(lambda: hn.bruteforce_top1(d_db, d_q, out=(bidx, bsim)),
+                        max(1, args.bf_steps), 1, torch)
+        hq, bq = q * args.steps / sec, q * max(1, args.bf_steps) / bsec
+        row = {"k": k, "alpha": alpha, "hn_queries_per_s": round(hq, 1),
+               "bruteforce_queries_per_s": round(bq, 1), "speedup": round(hq / bq, 2),
+               "pruned_pct": round(float(100.0 * (1.0 - aux["survivors"].double().mean() / n)), 4),
+               "exact_vs_bruteforce": bool(torch.equal(idx, bidx) and torch.equal(sim, bsim)),
+               "paper_cpu_speedup": p_speed, "paper_phase2_pct": p_ph2}
+        log(str(row))
+        rows.append(row)
+        ix.close()
+    print(json.dumps({"metric": "HN speed-up over the GPU brute force on the Table 3 grid",
+                      "unit": "x", "n_gpus": 1, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "hn_table3_n500k", "n": n, "queries": q,
+                                 "clusters": nc},
+                      "note": "paper figures: CPU (Core Ultra 7 256V) on UBC trevi "
+                              "descriptors; context, not a target",
+                      "rows": rows}), flush=True)
+
+
 def copy_probe(mib):
     """A plain copy kernel of known size for counter calibration: 5 copies of
     mib MiB (torch's device copy)."""
@@ -219,23 +370,38 @@ def timed(fn, steps, warmup, torch):
     return ev0.elapsed_time(ev1) / 1e3, wall
 
 
-def cpu_baseline(db, qs, k, alpha, budget_s):
+def cpu_baseline(db, qs, k, alpha, budget_s, gpu_idx=None, gpu_sim=None):
     """The CPU oracle's branch-and-bound (Algorithm 1, float64) on the same
     database, over consecutive query batches until about budget_s seconds of
-    work have been timed (or every query is done)."""
+    work have been timed (or every query is done).  With the GPU's results,
+    also the comparison on the sampled queries (indices equal, largest
+    |sim difference|) and the oracle's Phase-2 fraction."""
+    import numpy as np
+
     import oracle
     threads = min(16, oracle.default_threads())
     done, spent, batch = 0, 0.0, max(threads, 16)
+    idx, sim, ph2 = [], [], []
     while done < len(qs) and spent < budget_s:
         n = min(batch, len(qs) - done)
         t0 = time.perf_counter()
-        oracle.bnb_top1(db, qs[done:done + n], k, alpha, threads=threads)
+        r = oracle.bnb_top1(db, qs[done:done + n], k, alpha, threads=threads)
         spent += time.perf_counter() - t0
+        idx.append(r["idx"])
+        sim.append(r["sim"])
+        ph2.append(r["phase2"])
         done += n
         batch = min(4 * batch, max(threads, int(n * budget_s / max(spent, 1e-3))))
-    return {"value": done / spent, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d of %d queries, full database (N=%d), float64 "
-                      "branch-and-bound (Algorithm 1), %.1f s" % (done, len(qs), len(db), spent)}
+    res = {"value": done / spent, "unit": "queries/s", "cores": threads, "kind": "oracle",
+           "sample": "first %d of %d queries, full database (N=%d), float64 "
+                     "branch-and-bound (Algorithm 1), %.1f s" % (done, len(qs), len(db), spent)}
+    if gpu_idx is not None:
+        oi, osim = np.concatenate(idx), np.concatenate(sim)
+        res["oracle_check"] = {
+            "queries": done, "idx_equal": bool((oi == gpu_idx[:done]).all()),
+            "max_abs_dsim": float(np.abs(osim - gpu_sim[:done]).max()),
+            "oracle_phase2_pct": round(float(100.0 * np.concatenate(ph2).mean() / len(db)), 4)}
+    return res
 
 
 def gpu_time(fn, reps, torch):
@@ -395,6 +561,12 @@ def main():
     if args.workload == 4:
         bench_batched(args)
         return
+    if args.workload == 6:
+        bench_stream(args)
+        return
+    if args.table3:
+        bench_table3(args)
+        return
     import numpy as np
     import torch
 
@@ -459,9 +631,26 @@ def main():
                 "algorithmic": "2*Q*N*K / %d launches per step = %.4g flop per launch" % (
                     per_step, flops)}
 
+    # every scan pass: time per launch, algorithmic flop rate, K-prefix stream
+    # bytes read per launch and their rate
+    elem = {"f32": 4, "bf16": 2, "fp8": 1, "int8": 1}
+    passes = {}
+    for kname, kv in kernels.items():
+        if not kname.startswith("scan_"):
+            continue
+        per = kv["launches"] / args.steps
+        t = kv["avg_ms"] / 1e3
+        sbytes = w.n * w.k * elem[kname.rsplit("_", 1)[1]]
+        passes[kname] = {"avg_ms": round(kv["avg_ms"], 4),
+                         "tflops": round(acc.scan_flops(Q, w.n, w.k) / per / t / 1e12, 2),
+                         "stream_bytes": sbytes,
+                         "stream_gbs": round(sbytes / t / 1e9, 1),
+                         "frac_hbm": round(sbytes / t / 1e9 / PEAK["hbm_gbs"], 4)}
+
     # exactness of this run against the GPU exhaustive search, pruned fraction
     _, _, aux = ix.search(d_q, aux=True, **kw)
     surv = aux["survivors"].double()
+    slack_mean = float(torch.nan_to_num(aux["slack"], nan=0.0).mean())
     pruned_pct = float(100.0 * (1.0 - surv.mean() / w.n))
     out = {}
     if not args.no_bruteforce:
@@ -563,7 +752,9 @@ def main():
                    "rescoring": "f64"},
         "pruned_pct": round(pruned_pct, 4),
         "survivors_per_query": round(float(surv.mean()), 2),
+        "slack_mean": slack_mean,
         "roofline": roofline,
+        "passes": passes,
         "kernels": {k: {"avg_ms": round(v["avg_ms"], 4), "launches": v["launches"]}
                     for k, v in kernels.items()},
         "forms_queries_per_s": forms,
@@ -578,7 +769,8 @@ def main():
         res["topk"] = topk_res
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        res["cpu_baseline"] = cpu_baseline(db, qs, w.k, w.alpha, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(db, qs, w.k, w.alpha, args.cpu_seconds,
+                                           idx.cpu().numpy(), sim.cpu().numpy())
     print(json.dumps(res), flush=True)
     ix.close()
 

@@ -20,6 +20,9 @@
  *  - Every function returns HN_OK (0) or a negative hn_status and never
  *    throws.  On error no output is written and hn_last_error() returns a
  *    message for the calling thread.
+ *  - Arrays of 128-value float32 rows (databases, queries, HN-layer inputs
+ *    and outputs) are read and written with 16-byte accesses: their base
+ *    pointers must be 16-byte aligned, else HN_ERR_INVALID_ARG.
  *  - Indices are 0-based int64 positions in the database as given to the
  *    build; ties in similarity go to the smallest index.
  *  - Similarities are the canonical float64 sim: acc = 0; for j = 0..127:

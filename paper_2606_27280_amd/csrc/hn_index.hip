@@ -114,47 +114,63 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
     return r;
 }
 
-// One thread per row: float64 block norms, the Eq. 1 check, and the maxima.
-__global__ __launch_bounds__(256) void build_norms(const float *__restrict__ db, int64_t n,
+// Half a wave per row (four elements per lane, 16-byte loads): float64 block
+// norms, the Eq. 1 check and the maxima over the rows; a grid-stride loop so
+// each work-group issues one set of atomics.
+__global__ __launch_bounds__(256) void build_norms(const float4 *__restrict__ db, int64_t n,
                                                    int k, double alpha, BuildStats *st) {
     __shared__ double sh[4];
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
+    const double tol = ldexp(1.0, -13);
+    const double cM = sqrt(1.0 - alpha), cm = sqrt(alpha);
     double nM = 0, nm = 0, nf = 0, nM16 = 0, r16 = 0, amax = 0;
-    if (i < n) {
-        const float *x = db + i * kDim;
-        double sM = 0, sm = 0, s16 = 0, sr = 0;
-        bool finite = true;
-        for (int j = 0; j < kDim; ++j) {
-            float v = x[j];
-            finite = finite && isfinite(v);
-            double dv = (double)v;
-            if (j < k) {
-                amax = fmax(amax, fabs(dv));
+    for (int64_t r = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 2 + h; r < n;
+         r += (int64_t)gridDim.x * 8) {
+        const float4 x4 = db[r * 32 + l];
+        const float xv[4] = {x4.x, x4.y, x4.z, x4.w};
+        double sM = 0, sm = 0, s16 = 0, sr = 0, am = 0;
+        int bad = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float v = xv[u];
+            bad |= !isfinite(v);
+            const double dv = (double)v;
+            if (4 * l + u < k) {
+                am = fmax(am, fabs(dv));
                 sM = fma(dv, dv, sM);
-                double b = (double)bf16_round(v);
+                const double b = (double)bf16_round(v);
                 s16 = fma(b, b, s16);
                 sr = fma(b - dv, b - dv, sr);
             } else {
                 sm = fma(dv, dv, sm);
             }
         }
-        nM = sqrt(sM);
-        nm = sqrt(sm);
-        nf = sqrt(sM + sm);
-        nM16 = sqrt(s16);
-        r16 = sqrt(sr);
-        const double tol = ldexp(1.0, -13);
-        double cM = sqrt(1.0 - alpha), cm = sqrt(alpha);
-        bool ok = finite && fabs(nM - cM) <= tol * cM &&
-                  (alpha > 0.0 ? fabs(nm - cm) <= tol * cm : nm <= ldexp(1.0, -20));
-        if (!ok) {
-            atomicAdd(&st->bad_rows, 1ull);
-            atomicMin(&st->first_bad, (long long)i);
+        for (int o = 16; o > 0; o >>= 1) {
+            sM += __shfl_xor(sM, o);
+            sm += __shfl_xor(sm, o);
+            s16 += __shfl_xor(s16, o);
+            sr += __shfl_xor(sr, o);
+            am = fmax(am, __shfl_xor(am, o));
+            bad |= __shfl_xor(bad, o);
         }
-        if (!finite) {
-            atomicAdd(&st->nonfinite_rows, 1ull);
-            nM = nm = nf = nM16 = r16 = amax = 0;
+        const bool finite = !bad;
+        const double rM = sqrt(sM), rm = sqrt(sm);
+        const bool ok = finite && fabs(rM - cM) <= tol * cM &&
+                        (alpha > 0.0 ? fabs(rm - cm) <= tol * cm : rm <= ldexp(1.0, -20));
+        if (l == 0) {
+            if (!ok) {
+                atomicAdd(&st->bad_rows, 1ull);
+                atomicMin(&st->first_bad, (long long)r);
+            }
+            if (!finite) atomicAdd(&st->nonfinite_rows, 1ull);
         }
+        if (!finite) continue;
+        nM = fmax(nM, rM);
+        nm = fmax(nm, rm);
+        nf = fmax(nf, sqrt(sM + sm));
+        nM16 = fmax(nM16, sqrt(s16));
+        r16 = fmax(r16, sqrt(sr));
+        amax = fmax(amax, am);
     }
     double a = block_max<256>(nM, sh);
     double b = block_max<256>(nm, sh);
@@ -205,9 +221,9 @@ __global__ __launch_bounds__(256) void build_major8(const float *__restrict__ db
     const float amax = (float)sim_of_key(st->key_amax);
     const float scale = fp8_scale_for(amax), scale_i = int8_scale_for(amax);
     const float inv = 1.0f / scale, inv_i = 1.0f / scale_i;  // exact: powers of two
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double rn = 0, rr = 0, rni = 0, rri = 0;
-    if (i < n_pad) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_pad;
+         i += (int64_t)gridDim.x * 256) {
         double sn = 0, sr = 0, sni = 0, sri = 0;
         for (int c = 0; c < k8; ++c) {
             const float v = (i < n && c < k) ? db[i * kDim + c] : 0.0f;
@@ -223,10 +239,10 @@ __global__ __launch_bounds__(256) void build_major8(const float *__restrict__ db
             sri = fma(bi - (double)v, bi - (double)v, sri);
         }
         if (i < n) {
-            rn = sqrt(sn);
-            rr = sqrt(sr);
-            rni = sqrt(sni);
-            rri = sqrt(sri);
+            rn = fmax(rn, sqrt(sn));
+            rr = fmax(rr, sqrt(sr));
+            rni = fmax(rni, sqrt(sni));
+            rri = fmax(rri, sqrt(sri));
         }
     }
     const double a = block_max<256>(rn, sh);
@@ -307,6 +323,7 @@ extern "C" int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, 
     if (!out) return fail(HN_ERR_INVALID_ARG, "out is null");
     *out = nullptr;
     if (!db) return fail(HN_ERR_INVALID_ARG, "db is null");
+    if (!aligned16(db)) return fail(HN_ERR_INVALID_ARG, "db must be 16-byte aligned");
     if (d != kDim) return fail(HN_ERR_INVALID_ARG, "d must be 128 (got %d)", d);
     if (k < 1 || k > kDim - 1) return fail(HN_ERR_INVALID_ARG, "k must be in [1,127] (got %d)", k);
     if (!(alpha >= 0.0 && alpha < 1.0)) return fail(HN_ERR_INVALID_ARG, "alpha must be in [0,1)");
@@ -342,13 +359,14 @@ extern "C" int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, 
         return cleanup(HN_ERR_OOM);
     }
     hipLaunchKernelGGL(build_stats_init, dim3(1), dim3(64), 0, s, st);
-    hipLaunchKernelGGL(build_norms, dim3(grid_for(n, 256)), dim3(256), 0, s, db, n, k, alpha, st);
+    hipLaunchKernelGGL(build_norms, dim3(std::min(grid_for(n, 8), 4096u)), dim3(256), 0, s,
+                       reinterpret_cast<const float4 *>(db), n, k, alpha, st);
     hipLaunchKernelGGL(build_major32, dim3(grid_for(ix->n_pad * ix->kp, 256)), dim3(256), 0, s,
                        db, n, ix->n_pad, k, ix->kp, ix->major32);
     hipLaunchKernelGGL(build_major16, dim3(grid_for(ix->n_pad * ix->kb, 256)), dim3(256), 0, s,
                        db, n, ix->n_pad, k, ix->kb, ix->major16);
     if (ix->k8)
-        hipLaunchKernelGGL(build_major8, dim3(grid_for(ix->n_pad, 256)), dim3(256), 0, s, db, n,
+        hipLaunchKernelGGL(build_major8, dim3(std::min(grid_for(ix->n_pad, 256), 4096u)), dim3(256), 0, s, db, n,
                            ix->n_pad, k, ix->k8, st, ix->major8, ix->major_i8);
     hipError_t e = hipMemcpyAsync(ix->rows, db, (size_t)n * kDim * sizeof(float),
                                   hipMemcpyDeviceToDevice, s);

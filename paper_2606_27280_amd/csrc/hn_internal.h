@@ -16,6 +16,9 @@ constexpr int kXcds = 8;      // MI355X accelerator complex dies
 
 // Set the calling thread's error message and return `code`.
 int fail(int code, const char *fmt, ...);
+// Rows of 128 float32 values are read with 16-byte loads: their base pointer
+// must be 16-byte aligned.
+inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 void clear_error();
 
 #define HN_HIP(call)                                                                   \

@@ -170,6 +170,8 @@ extern "C" int hn_layer_forward(const float *f, int64_t b, int32_t d, int32_t k,
     if (rc) return rc;
     if (b == 0) return HN_OK;
     if (!f || !out) return fail(HN_ERR_INVALID_ARG, "null pointer argument");
+    if (!aligned16(f) || !aligned16(out))
+        return fail(HN_ERR_INVALID_ARG, "f and out must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     ProfScope prof_(s, "hn_layer_fwd");
     hipLaunchKernelGGL(layer_fwd, dim3(blocks_of_rows(b, kRowsFwd)), dim3(256), 0, s,
@@ -186,6 +188,8 @@ extern "C" int hn_layer_backward(const float *f, const float *g, int64_t b, int3
     if (rc) return rc;
     if (b == 0) return HN_OK;
     if (!f || !g || !grad) return fail(HN_ERR_INVALID_ARG, "null pointer argument");
+    if (!aligned16(f) || !aligned16(g) || !aligned16(grad))
+        return fail(HN_ERR_INVALID_ARG, "f, g and grad must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     ProfScope prof_(s, "hn_layer_bwd");
     hipLaunchKernelGGL(layer_bwd, dim3(blocks_of_rows(b, kRowsBwd)), dim3(256), 0, s,

@@ -529,6 +529,7 @@ extern "C" int hn_multi_search(hn_multi_plan *plan, const float *queries, int64_
     if (!plan) return fail(HN_ERR_INVALID_ARG, "null plan");
     if (plan->total_q == 0) return HN_OK;
     if (!queries || !out_idx || !out_sim) return fail(HN_ERR_INVALID_ARG, "null queries or outputs");
+    if (!aligned16(queries)) return fail(HN_ERR_INVALID_ARG, "queries must be 16-byte aligned");
     hipStream_t s = (hipStream_t)stream;
     if (!use_graph) return enqueue(plan, queries, out_idx, out_sim, s);
     if (!plan->exec || plan->g_q != queries || plan->g_idx != out_idx || plan->g_sim != out_sim) {

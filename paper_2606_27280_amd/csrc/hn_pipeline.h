@@ -844,19 +844,40 @@ __global__ __launch_bounds__(256) void topk_select(const int64_t *__restrict__ o
 
 // ------------------------------------------------- brute-force helpers
 
-__global__ __launch_bounds__(256) void bf_db_norm(const float *__restrict__ db, int64_t n,
+// Largest row norm of the database (an upper bound after the caller's
+// 2^-40 widening, which covers the float64 summation in any order).  Half a
+// wave per row, four elements per lane with 16-byte loads, kBfNormRows rows
+// per wave loaded before any arithmetic: a streaming read at copy speed.  The
+// grid is capped and strides over the rows, so few work-groups contend for
+// the one atomic maximum.
+constexpr int kBfNormRows = 16;
+constexpr unsigned kBfNormGrid = 4096;
+
+__global__ __launch_bounds__(256) void bf_db_norm(const float4 *__restrict__ db, int64_t n,
                                                   unsigned long long *mu_key) {
     __shared__ double sh[4];
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double v = 0.0;
-    if (i < n) {
-        const float *x = db + i * kDim;
-        double s = 0.0;
-        for (int j = 0; j < kDim; ++j) s = fma((double)x[j], (double)x[j], s);
-        v = sqrt(s);
+    const int lane = threadIdx.x & 63, h = lane >> 5, l = lane & 31;
+    double m = 0.0;
+    for (int64_t r0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kBfNormRows; r0 < n;
+         r0 += (int64_t)gridDim.x * 4 * kBfNormRows) {
+        float4 v[kBfNormRows / 2];
+#pragma unroll
+        for (int t = 0; t < kBfNormRows / 2; ++t) {
+            const int64_t r = r0 + 2 * t + h;
+            v[t] = r < n ? db[r * 32 + l] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+#pragma unroll
+        for (int t = 0; t < kBfNormRows / 2; ++t) {
+            double ss = (double)v[t].x * v[t].x;
+            ss = fma((double)v[t].y, (double)v[t].y, ss);
+            ss = fma((double)v[t].z, (double)v[t].z, ss);
+            ss = fma((double)v[t].w, (double)v[t].w, ss);
+            for (int o = 16; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+            m = fmax(m, ss);
+        }
     }
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    m = fmax(m, __shfl_xor(m, 32));
+    if (lane == 0) sh[threadIdx.x >> 6] = sqrt(m);
     __syncthreads();
     if (threadIdx.x == 0)
         atomicMax(mu_key, key_of(fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]))));
@@ -901,26 +922,38 @@ __global__ __launch_bounds__(256) void bf_prep(BfPrepArgs P) {
     P.qflag[i] = 0;
 }
 
+// Largest chunk partial of query i: one wave per query, lanes striding over
+// the chunks (many independent loads in flight), then a wave maximum.
+__device__ __forceinline__ float chunk_max(const float *part_val, int32_t n_chunks, int32_t q_pad,
+                                           int64_t i, int lane) {
+    float m = -INFINITY;
+#pragma unroll 8
+    for (int c = lane; c < n_chunks; c += 64) m = fmaxf(m, part_val[(int64_t)c * q_pad + i]);
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    return m;
+}
+
+// Exhaustive-scan threshold: the scan maximum minus the window, per query
+// (launch: blocks_for(q, 4) groups of 4 waves).
 __global__ __launch_bounds__(256) void bf_threshold(const float *part_val, int32_t n_chunks,
                                                     int32_t q_pad, int64_t q, const double *win,
                                                     float *thr) {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= q) return;
-    float m = -INFINITY;
-    for (int c = 0; c < n_chunks; ++c) m = fmaxf(m, part_val[(int64_t)c * q_pad + i]);
-    thr[i] = __double2float_rd((double)m - win[i]);
+    const float m = chunk_max(part_val, n_chunks, q_pad, i, threadIdx.x & 63);
+    if ((threadIdx.x & 63) == 0) thr[i] = __double2float_rd((double)m - win[i]);
 }
 
 // Single-pass re-filter threshold: max(T_q, m - w_q) with m the final scan
 // maximum over all chunks (which includes the starting value T_q + w_q).
+// Same launch shape as bf_threshold.
 __global__ __launch_bounds__(256) void win_threshold(const float *part_val, int32_t n_chunks,
                                                      int32_t q_pad, int64_t q, const double *win,
                                                      const float *thr, float *out) {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= q) return;
-    float m = -INFINITY;
-    for (int c = 0; c < n_chunks; ++c) m = fmaxf(m, part_val[(int64_t)c * q_pad + i]);
-    out[i] = fmaxf(thr[i], __double2float_rd((double)m - win[i]));
+    const float m = chunk_max(part_val, n_chunks, q_pad, i, threadIdx.x & 63);
+    if ((threadIdx.x & 63) == 0) out[i] = fmaxf(thr[i], __double2float_rd((double)m - win[i]));
 }
 
 __global__ void fill_lower(double *lower, int64_t *idx, int64_t q) {

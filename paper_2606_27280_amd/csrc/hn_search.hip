@@ -406,7 +406,7 @@ int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *o
         rc = launch_scan<kWindow>(W.precision, W.width, W.cfg, W.plan, A, s);
         if (rc) return rc;
         ProfScope prof_(s, "win_threshold");
-        hipLaunchKernelGGL(win_threshold, dim3(blocks_for(q)), dim3(256), 0, s, W.part_val,
+        hipLaunchKernelGGL(win_threshold, dim3(blocks_for(q, 4)), dim3(256), 0, s, W.part_val,
                            W.plan.n_chunks, (int32_t)W.plan.q_pad, q, W.win, W.thr, W.thr_ref);
     } else {
         rc = launch_scan<kFilter>(W.precision, W.width, W.cfg, W.plan, A, s);
@@ -566,6 +566,7 @@ extern "C" int hn_search_top1(const hn_index *ix, const float *queries, int64_t 
     if (q >= ((int64_t)1 << 31) - 4096) return fail(HN_ERR_UNSUPPORTED, "q must be < 2^31");
     if (q > 0 && (!queries || !out_idx || !out_sim))
         return fail(HN_ERR_INVALID_ARG, "null queries or outputs");
+    if (!aligned16(queries)) return fail(HN_ERR_INVALID_ARG, "queries must be 16-byte aligned");
     int rc = validate_opts(ix, opts);
     if (rc) return rc;
     if (stats) memset(stats, 0, sizeof *stats);
@@ -612,6 +613,7 @@ extern "C" int hn_search_topk(const hn_index *ix, const float *queries, int64_t 
     if (q >= ((int64_t)1 << 31) - 4096) return fail(HN_ERR_UNSUPPORTED, "q must be < 2^31");
     if (q > 0 && (!queries || !out_idx || !out_sim))
         return fail(HN_ERR_INVALID_ARG, "null queries or outputs");
+    if (!aligned16(queries)) return fail(HN_ERR_INVALID_ARG, "queries must be 16-byte aligned");
     int rc = validate_opts(ix, opts);
     if (rc) return rc;
     if (q == 0) return HN_OK;
@@ -691,6 +693,7 @@ extern "C" int hn_filter_survivors(const hn_index *ix, const float *queries, int
     if (!count) return fail(HN_ERR_INVALID_ARG, "count is null");
     if (q > 0 && (!queries || !lower || (cap > 0 && !pairs)))
         return fail(HN_ERR_INVALID_ARG, "null queries, lower bounds or pairs");
+    if (!aligned16(queries)) return fail(HN_ERR_INVALID_ARG, "queries must be 16-byte aligned");
     int rc = validate_opts(ix, opts);
     if (rc) return rc;
     *count = 0;
@@ -717,6 +720,7 @@ extern "C" int hn_scan_scores(const hn_index *ix, const float *queries, int64_t 
     if (!ix) return fail(HN_ERR_INVALID_ARG, "null index");
     if (q < 0) return fail(HN_ERR_INVALID_ARG, "q must be >= 0");
     if (q > 0 && (!queries || !scores)) return fail(HN_ERR_INVALID_ARG, "null queries or scores");
+    if (!aligned16(queries)) return fail(HN_ERR_INVALID_ARG, "queries must be 16-byte aligned");
     int rc = check_precision(ix, precision);
     if (rc) return rc;
     if (q == 0) return HN_OK;
@@ -783,6 +787,8 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     if (q < 0) return fail(HN_ERR_INVALID_ARG, "q must be >= 0");
     if (!db || (q > 0 && (!queries || !out_idx || !out_sim)))
         return fail(HN_ERR_INVALID_ARG, "null pointer argument");
+    if (!aligned16(db) || !aligned16(queries))
+        return fail(HN_ERR_INVALID_ARG, "db and queries must be 16-byte aligned");
     if (q == 0) return HN_OK;
     hipStream_t s = (hipStream_t)stream;
     const TileInfo ti = tile_info(HN_PREC_FP32, kDim);
@@ -843,7 +849,10 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     hipLaunchKernelGGL(zero_u64, dim3(1), dim3(64), 0, s, counter, 4);
     {
         ProfScope prof_(s, "bf_db_norm");
-        hipLaunchKernelGGL(bf_db_norm, dim3(blocks_for(n)), dim3(256), 0, s, db, n, mu_key);
+        const unsigned g = (unsigned)std::min<int64_t>(kBfNormGrid, (n + 4 * kBfNormRows - 1) /
+                                                                         (4 * kBfNormRows));
+        hipLaunchKernelGGL(bf_db_norm, dim3(g), dim3(256), 0, s,
+                           reinterpret_cast<const float4 *>(db), n, mu_key);
     }
     {
         PrepArgs P;
@@ -905,7 +914,7 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     if (rc) return rc;
     {
         ProfScope prof_(s, "bf_threshold");
-        hipLaunchKernelGGL(bf_threshold, dim3(blocks_for(q)), dim3(256), 0, s, part_val, p.n_chunks,
+        hipLaunchKernelGGL(bf_threshold, dim3(blocks_for(q, 4)), dim3(256), 0, s, part_val, p.n_chunks,
                            (int32_t)p.q_pad, q, win, thr);
     }
 

@@ -297,6 +297,17 @@ def test_invalid_inputs(hn):
         ix.search(dev(qs), precision=7)
     with pytest.raises(hn.HNError):
         ix.search(dev(qs), beta=0.5)
+    say("misaligned row pointers")
+    buf = torch.zeros(len(qs) * 128 + 1, dtype=torch.float32, device="cuda:0")
+    shifted = buf[1:].view(len(qs), 128)  # contiguous, 4 bytes past a 16-byte boundary
+    shifted.copy_(dev(qs))
+    with pytest.raises(hn.HNError) as e:
+        ix.search(shifted)
+    assert e.value.code == -1 and "aligned" in str(e.value)
+    with pytest.raises(hn.HNError):
+        hn.bruteforce_top1(dev(db), shifted)
+    with pytest.raises(hn.HNError):
+        hn.hn_layer(shifted, k, alpha)
     ix.close()
     say("fp8 on k = 40 (no fp8 copy)")
     db40 = hn_inputs.make_db(300, 40, alpha, 3, 8)
