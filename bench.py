@@ -286,7 +286,18 @@ def bench_table3(args):
         bsec, _ = timed(lambda: hn.bruteforce_top1(d_db, d_q, out=(bidx, bsim)),
                         max(1, args.bf_steps), 1, torch)
         hq, bq = q * args.steps / sec, q * max(1, args.bf_steps) / bsec
+        # the same search as a one-database plan replayed from a HIP graph
+        # (no allocation, no host work between the kernels)
+        plan = hn.MultiPlan([ix], [q])
+        gi = torch.empty(q, dtype=torch.int64, device=dev)
+        gs = torch.empty(q, dtype=torch.float64, device=dev)
+        gsec, _ = timed(lambda: plan.search(d_q, out=(gi, gs)), args.steps, args.warmup, torch)
+        gq = q * args.steps / gsec
+        graph_exact = bool(torch.equal(gi, idx) and torch.equal(gs, sim))
+        plan.close()
         row = {"k": k, "alpha": alpha, "hn_queries_per_s": round(hq, 1),
+               "hn_graph_queries_per_s": round(gq, 1), "graph_speedup": round(gq / bq, 2),
+               "graph_same_result": graph_exact,
                "bruteforce_queries_per_s": round(bq, 1), "speedup": round(hq / bq, 2),
                "pruned_pct": round(float(100.0 * (1.0 - aux["survivors"].double().mean() / n)), 4),
                "exact_vs_bruteforce": bool(torch.equal(idx, bidx) and torch.equal(sim, bsim)),

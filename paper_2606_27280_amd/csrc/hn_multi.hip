@@ -45,10 +45,10 @@ __global__ __launch_bounds__(256) void prep_multi(const PrepArgs *__restrict__ P
                                                   const DbRef *__restrict__ db,
                                                   const int32_t *__restrict__ gdb,
                                                   int64_t total_pad) {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (g >= total_pad) return;
-    const int d = gdb[g];
-    prep_one(P[d], g - db[d].pad_base);
+    const int d = __builtin_amdgcn_readfirstlane(gdb[g]);
+    prep_wave(P[d], g - db[d].pad_base, threadIdx.x & 63);
 }
 
 __global__ __launch_bounds__(256) void seed_multi(const SeedArgs *__restrict__ S,
@@ -121,7 +121,7 @@ int enqueue(hn_multi_plan *P, const float *queries, int64_t *out_idx, double *ou
                        P->total_q, reinterpret_cast<float4 *>(P->q_buf));
     {
         ProfScope prof_(s, "multi_prep");
-        hipLaunchKernelGGL(prep_multi, dim3(blocks_for(P->total_pad)), dim3(256), 0, s, P->preps,
+        hipLaunchKernelGGL(prep_multi, dim3(blocks_for(P->total_pad, 4)), dim3(256), 0, s, P->preps,
                            P->dbref, P->gdb, P->total_pad);
     }
     for (int g = 0; g < ng; ++g) {

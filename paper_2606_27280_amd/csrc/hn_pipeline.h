@@ -55,38 +55,58 @@ struct PrepArgs {
     unsigned *work;
 };
 
-// Query i (of the padded batch): norms and the float32 / bf16 / fp8 operands.
-__device__ __forceinline__ void prep_one(const PrepArgs &P, const int64_t i) {
+__device__ __forceinline__ double wave_sum64(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Query i (of the padded batch), one wave: norms and the float32 / bf16 /
+// fp8 / int8 operands.  Each lane takes two of the 128 values (and operand
+// columns lane, lane + 64); the float64 sums are reduced across the wave and
+// every norm is rounded up by (1 + 2^-40), which covers their rounding in any
+// summation order.
+__device__ __forceinline__ void prep_wave(const PrepArgs &P, const int64_t i, const int lane) {
     if (i >= P.q_pad) return;
     if (i >= P.nq) {
-        if (P.op32)
-            for (int c = 0; c < P.w32; ++c) P.op32[i * P.w32 + c] = 0.0f;
-        if (P.op16)
-            for (int c = 0; c < P.w16; ++c) P.op16[i * P.w16 + c] = 0;
-        if (P.op8)
-            for (int c = 0; c < P.w8; ++c) P.op8[i * P.w8 + c] = 0;
-        if (P.opi)
-            for (int c = 0; c < P.w8; ++c) P.opi[i * P.w8 + c] = 0;
+        for (int c = lane; c < P.w32; c += 64)
+            if (P.op32) P.op32[i * P.w32 + c] = 0.0f;
+        for (int c = lane; c < P.w16; c += 64)
+            if (P.op16) P.op16[i * P.w16 + c] = 0;
+        if (lane < P.w8) {
+            if (P.op8) P.op8[i * P.w8 + lane] = 0;
+            if (P.opi) P.opi[i * P.w8 + lane] = 0;
+        }
         return;
     }
     const int k = P.k;
     const float *v = P.q + i * kDim;
+    const float2 f2 = reinterpret_cast<const float2 *>(v)[lane];
     double sM = 0, sm = 0, sr = 0;
     float amax = 0.0f;
-    bool finite = true;
-    for (int j = 0; j < kDim; ++j) {
-        float f = v[j];
-        finite = finite && isfinite(f);
-        double d = (double)f;
+    int bad = 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int j = 2 * lane + u;
+        const float f = u ? f2.y : f2.x;
+        bad |= !isfinite(f);
+        const double d = (double)f;
         if (j < k) {
             sM = fma(d, d, sM);
-            double b = (double)bf16_rne(f);
+            const double b = (double)bf16_rne(f);
             sr = fma(b - d, b - d, sr);
             amax = fmaxf(amax, fabsf(f));
         } else {
             sm = fma(d, d, sm);
         }
     }
+    sM = wave_sum64(sM);
+    sm = wave_sum64(sm);
+    sr = wave_sum64(sr);
+    for (int o = 32; o > 0; o >>= 1) {
+        amax = fmaxf(amax, __shfl_xor(amax, o));
+        bad |= __shfl_xor(bad, o);
+    }
+    const bool finite = !bad;
     const double up = 1.0 + ldexp(1.0, -40);
     QNorm r;
     r.major = sqrt(sM) * up;
@@ -98,48 +118,48 @@ __device__ __forceinline__ void prep_one(const PrepArgs &P, const int64_t i) {
     r.resi = 0.0;
     r.sci = 1.0f;
     r.bad = finite ? 0 : 1;
-    if (P.op32)
-        for (int c = 0; c < P.w32; ++c) P.op32[i * P.w32 + c] = (c < k && finite) ? v[c] : 0.0f;
-    if (P.op16)
-        for (int c = 0; c < P.w16; ++c)
+    for (int c = lane; c < P.w32; c += 64)
+        if (P.op32) P.op32[i * P.w32 + c] = (c < k && finite) ? v[c] : 0.0f;
+    for (int c = lane; c < P.w16; c += 64)
+        if (P.op16)
             P.op16[i * P.w16 + c] =
                 (c < k && finite) ? (uint16_t)(__float_as_uint(bf16_rne(v[c])) >> 16) : 0;
+    // fp8 / int8 (w8 <= 32): lane c codes column c
+    const float f8 = (lane < P.w8 && lane < k && finite) ? v[lane] : 0.0f;
     if (P.op8) {
         const float sc = finite ? fp8_scale_for(amax) : 1.0f;
         const float inv = 1.0f / sc;  // exact: a power of two
-        double s8 = 0;
-        for (int c = 0; c < P.w8; ++c) {
-            const float f = (c < k && finite) ? v[c] : 0.0f;
-            const uint8_t code = fp8_e4m3(f * inv);
-            P.op8[i * P.w8 + c] = code;
-            const double e = (double)fp8_e4m3_value(code) * (double)sc - (double)f;
-            s8 = fma(e, e, s8);
+        double e2 = 0.0;
+        if (lane < P.w8) {
+            const uint8_t code = fp8_e4m3(f8 * inv);
+            P.op8[i * P.w8 + lane] = code;
+            const double e = (double)fp8_e4m3_value(code) * (double)sc - (double)f8;
+            e2 = e * e;
         }
-        r.res8 = sqrt(s8) * up;
+        r.res8 = sqrt(wave_sum64(e2)) * up;
         r.sc8 = sc;
     }
     if (P.opi) {
         const float sc = finite ? int8_scale_for(amax) : 1.0f;
         const float inv = 1.0f / sc;  // exact: a power of two
-        double si = 0;
-        for (int c = 0; c < P.w8; ++c) {
-            const float f = (c < k && finite) ? v[c] : 0.0f;
-            const int8_t code = int8_code(f * inv);
-            P.opi[i * P.w8 + c] = code;
-            const double e = (double)code * (double)sc - (double)f;
-            si = fma(e, e, si);
+        double e2 = 0.0;
+        if (lane < P.w8) {
+            const int8_t code = int8_code(f8 * inv);
+            P.opi[i * P.w8 + lane] = code;
+            const double e = (double)code * (double)sc - (double)f8;
+            e2 = e * e;
         }
-        r.resi = sqrt(si) * up;
+        r.resi = sqrt(wave_sum64(e2)) * up;
         r.sci = sc;
     }
-    P.qn[i] = r;
+    if (lane == 0) P.qn[i] = r;
 }
 
-// One thread per (padded) query; also zeroes the scan bookkeeping words.
+// One wave per (padded) query, 4 per work-group; the first group also zeroes
+// the scan bookkeeping words.
 __global__ __launch_bounds__(256) void prep_queries(PrepArgs P) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (P.work && i < kWorkWords) P.work[i] = 0u;
-    prep_one(P, i);
+    if (P.work && blockIdx.x == 0 && (int)threadIdx.x < kWorkWords) P.work[threadIdx.x] = 0u;
+    prep_wave(P, (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6), threadIdx.x & 63);
 }
 
 // ---------------------------------------------------------------- seed
@@ -942,6 +962,16 @@ __global__ __launch_bounds__(256) void bf_threshold(const float *part_val, int32
     if (i >= q) return;
     const float m = chunk_max(part_val, n_chunks, q_pad, i, threadIdx.x & 63);
     if ((threadIdx.x & 63) == 0) thr[i] = __double2float_rd((double)m - win[i]);
+}
+
+// Largest prefix-pass score per (padded) query position: the exhaustive
+// scan's starting running maximum.  Same launch shape as bf_threshold.
+__global__ __launch_bounds__(256) void prefix_max(const float *part_val, int32_t n_chunks,
+                                                  int32_t ld, int64_t q_pad, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= q_pad) return;
+    const float m = chunk_max(part_val, n_chunks, ld, i, threadIdx.x & 63);
+    if ((threadIdx.x & 63) == 0) out[i] = m;
 }
 
 // Single-pass re-filter threshold: max(T_q, m - w_q) with m the final scan

@@ -817,17 +817,21 @@ inline Plan make_plan(int64_t n, int64_t q, int cfg, int chunk_blocks, int rows,
     p.n_qb = (int32_t)((q + qb - 1) / qb);
     p.q_pad = (int64_t)p.n_qb * qb;
     p.n_blocks = (int32_t)((n + rows - 1) / rows);
-    if (chunk_blocks <= 0 && slots >= kXcds) {
-        const int64_t max_chunks = std::max<int64_t>(1, p.n_blocks / 8);
-        const int64_t rounds = std::max<int64_t>(1, (target_items + slots / 2) / slots);
-        int64_t want = std::max<int64_t>(1, rounds * slots / p.n_qb);
+    if (chunk_blocks <= 0) {
+        // chunks of at least 32 blocks (a work item's fixed costs, its query
+        // tiles and its flush, then stay small against its scan), unless that
+        // leaves fewer than 256 items; never below 8 blocks
+        const int64_t max_chunks = std::max<int64_t>(
+            1, std::max<int64_t>(p.n_blocks / 32, std::min<int64_t>(p.n_blocks / 8, 256)));
+        int64_t want;
+        if (slots >= kXcds) {
+            const int64_t rounds = std::max<int64_t>(1, (target_items + slots / 2) / slots);
+            want = std::max<int64_t>(1, rounds * slots / p.n_qb);
+        } else {
+            want = std::max<int64_t>(1, (target_items + p.n_qb - 1) / p.n_qb);
+        }
         want = std::min(std::max(want, min_chunks), max_chunks);
         chunk_blocks = (int32_t)((p.n_blocks + want - 1) / want);
-    } else if (chunk_blocks <= 0) {
-        int64_t want_chunks = std::max<int64_t>(1, (target_items + p.n_qb - 1) / p.n_qb);
-        want_chunks = std::max(want_chunks, min_chunks);
-        chunk_blocks =
-            (int32_t)std::max<int64_t>(8, (p.n_blocks + want_chunks - 1) / want_chunks);
     }
     // a chunk is addressed through one buffer descriptor: below 2^31 bytes
     // for rows of up to 128 float32 values

@@ -69,7 +69,7 @@ void launch_prep(const hn_index *ix, const float *queries, int64_t q, int64_t q_
     P.qn = W.qn;
     P.work = W.work;
     ProfScope prof_(s, "prep_queries");
-    hipLaunchKernelGGL(prep_queries, dim3(blocks_for(q_pad)), dim3(256), 0, s, P);
+    hipLaunchKernelGGL(prep_queries, dim3(blocks_for(q_pad, 4)), dim3(256), 0, s, P);
 }
 
 int validate_opts(const hn_index *ix, const hn_search_opts *o) {
@@ -795,11 +795,13 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     const int cfg = pick_cfg(q, ti.cols, ti.cost, 2);
     Plan p = make_plan(n, q, cfg, 0, ti.rows, ti.cols, 8192,
                        scan_slots(HN_PREC_FP32, kWindow, kDim, cfg));
-    // A prefix pass (one chunk of the first n_pre rows) gives each query a
-    // starting running maximum: a real scan score, so never above the final
-    // maximum, and far fewer near-record candidates in the main pass.
+    // A prefix pass over the first n_pre rows gives each query a starting
+    // running maximum: a real scan score, so never above the final maximum,
+    // and far fewer near-record candidates in the main pass.  It runs as up
+    // to 16 chunks (work items in parallel) reduced to one maximum per query.
     const int64_t n_pre = std::min<int64_t>(n, 4096);
-    Plan pp = make_plan(n_pre, q, cfg, (int32_t)((n_pre + ti.rows - 1) / ti.rows), ti.rows,
+    const int32_t pre_blocks = (int32_t)((n_pre + ti.rows - 1) / ti.rows);
+    Plan pp = make_plan(n_pre, q, cfg, std::max<int32_t>(1, (pre_blocks + 15) / 16), ti.rows,
                         ti.cols);
     const int64_t cap = std::min<int64_t>(
         std::max<int64_t>(q * std::max<int64_t>(256, 16 * (int64_t)p.n_chunks), 1 << 16),
@@ -809,7 +811,8 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     auto add = [&](size_t count, size_t sz) { bytes += (count * sz + 255) & ~size_t(255); };
     add(p.q_pad, sizeof(QNorm));
     add((size_t)p.n_chunks * p.q_pad, 4);
-    add(p.q_pad, 4);
+    add((size_t)pp.n_chunks * pp.q_pad, 4);
+    add((size_t)pp.n_chunks * pp.q_pad, 4);
     add(p.q_pad, 4);
     add(p.q_pad, 4);
     add(q, 8);
@@ -829,8 +832,9 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     if (rc) return rc;
     QNorm *qn = ar->take<QNorm>(p.q_pad);
     float *part_val = ar->take<float>((size_t)p.n_chunks * p.q_pad);
-    float *pre_val = ar->take<float>(p.q_pad);
-    int32_t *pre_idx = ar->take<int32_t>(p.q_pad);
+    float *pre_val = ar->take<float>((size_t)pp.n_chunks * pp.q_pad);
+    int32_t *pre_idx = ar->take<int32_t>((size_t)pp.n_chunks * pp.q_pad);
+    float *pre_max = ar->take<float>(p.q_pad);
     float *win_scan = ar->take<float>(p.q_pad);
     double *win = ar->take<double>(q);
     float *thr = ar->take<float>(q);
@@ -863,7 +867,7 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
         P.k = kDim - 1;
         P.qn = qn;
         P.work = work;
-        hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad)), dim3(256), 0, s, P);
+        hipLaunchKernelGGL(prep_queries, dim3(blocks_for(p.q_pad, 4)), dim3(256), 0, s, P);
     }
     BfPrepArgs P{qn, mu_key, q, p.q_pad, win_scan, win, best_key, best_idx, cnt, qflag, counter};
     {
@@ -903,7 +907,12 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     A.part_val = part_val;
     A.part_idx = nullptr;
     A.thr = win_scan;
-    A.init_best = pre_val;
+    {
+        ProfScope prof_(s, "bf_prefix_max");
+        hipLaunchKernelGGL(prefix_max, dim3(blocks_for(p.q_pad, 4)), dim3(256), 0, s, pre_val,
+                           pp.n_chunks, (int32_t)pp.q_pad, p.q_pad, pre_max);
+    }
+    A.init_best = pre_max;
     A.pairs = pairs;
     A.pair_val = pair_val;
     A.counter = counter;
