@@ -22,6 +22,7 @@
 #pragma once
 
 #include <algorithm>
+#include <climits>
 
 #include "hn_internal.h"
 
@@ -66,12 +67,14 @@ struct ScanArgs {
 // 16x16 output: lane l holds column l % 16 and rows 4 (l / 16) + v.
 struct Shape16 {
     static constexpr int kRows = 16, kCols = 16, kGroups = 4, kAcc = 4;
+    static constexpr bool kIntScores = false;  // exact integer sums (mma_i)
     typedef v4f Acc;
     __device__ __forceinline__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 // 32x32 output: lane l holds column l % 32 and rows 8 (v / 4) + 4 (l / 32) + v % 4.
 struct Shape32 {
     static constexpr int kRows = 32, kCols = 32, kGroups = 2, kAcc = 16;
+    static constexpr bool kIntScores = false;  // exact integer sums (mma_i)
     typedef v16f Acc;
     __device__ __forceinline__ static int out_row(int lane, int v) {
         return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -286,7 +289,10 @@ struct I8Tile32 : Shape32 {
     static constexpr int kFragRegs = kSlice / 4;
     typedef Regs<kFragRegs> Frag;
     HN_SAME_Q_OPERAND
-    __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
+    // The filter compares these exact int32 sums with integer thresholds; the
+    // other modes take them as float32 (exact: |sum| < 2^24).
+    static constexpr bool kIntScores = true;
+    __device__ __forceinline__ static v16i mma_i(const Frag &x, const Frag &q) {
         v16i acc = {};
 #pragma unroll
         for (int c = 0; c < kSlice / 8; ++c) {
@@ -294,6 +300,10 @@ struct I8Tile32 : Shape32 {
             const long b = (long)((unsigned long)q.v[2 * c] | ((unsigned long)q.v[2 * c + 1] << 32));
             acc = __builtin_amdgcn_mfma_i32_32x32x16_i8(a, b, acc, 0, 0, 0);
         }
+        return acc;
+    }
+    __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
+        const v16i acc = mma_i(x, q);
         Acc out;
 #pragma unroll
         for (int v = 0; v < 16; ++v) out[v] = (float)acc[v];
@@ -383,10 +393,9 @@ __device__ __forceinline__ void flush_pairs(const ScanArgs &A, EmitBuf &B) {
 // Padding queries never pass: the caller's threshold for them is +inf (or a
 // window limit of +inf / NaN), so the slot test is one comparison, whose lane
 // mask is the ballot itself.
-template <class Tile, bool WithVal, bool Direct>
-__device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B,
-                                           const typename Tile::Acc &a, float t, int q,
-                                           int eblk) {
+template <class Tile, bool WithVal, bool Direct, class AccT, class T>
+__device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B, const AccT &a, T t,
+                                           int q, int eblk) {
     const int lane = (int)__lane_id();
 #pragma unroll
     for (int v0 = 0; v0 < Tile::kAcc; v0 += 4) {
@@ -416,7 +425,7 @@ __device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B,
             if (pv[u]) {
                 const int pos = off + (int)lane_prefix(mv[u]);
                 B.pairs[pos] = make_int2(A.q_base + q, eblk + Tile::out_row(lane, v0 + u));
-                if (WithVal) B.vals[pos] = a[v0 + u];
+                if constexpr (WithVal) B.vals[pos] = a[v0 + u];
             }
             off += c[u];
         }
@@ -497,7 +506,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
     // row and ending at its last row (or the database end): a block's load
     // is the lane's fixed byte offset plus the block's, with no per-lane
     // address arithmetic, and rows past the database end read as zeros.
-    // make_plan keeps a chunk below 2^31 bytes.
+    // make_plan keeps a chunk within 2^30 bytes.
     const int64_t row0 = (int64_t)blk0 * R;
     const int row_bytes = A.x_stride * (int)sizeof(Elem);
     const int64_t rows_in = min((int64_t)blk1 * R, A.n) - row0;
@@ -513,19 +522,64 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
 #define HN_PF_WIDE 1
 #endif
     constexpr int PF = Tile::kFragRegs <= 2 ? 8 : (Tile::kFragRegs <= 4 ? 4 : HN_PF_WIDE);
-    const int blk_last = max(blk1 - 1, 0);
+    // Loads past the item's end (the last group's prefetch) fall outside the
+    // descriptor's range and read zeros without touching memory; they are
+    // never used.
+    const int blk_step = R * row_bytes;
     auto load_group = [&](Frag (&xg)[PF], int gbase) {
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
-            const int b = min(gbase + j * NS, blk_last);
-            xg[j].load_buf(xrsrc, lane_off + (b - blk0) * (R * row_bytes));
+            // block offset in a scalar register: one vector add per load
+            const int boff =
+                __builtin_amdgcn_readfirstlane((gbase - blk0 + j * NS) * blk_step);
+            xg[j].load_buf(xrsrc, lane_off + boff);
         }
     };
+    // integer filter: the float threshold t as the least integer >= t
+    // (clamped to +-2^24, beyond every exact int8 sum); padding queries
+    // (t = +inf) never pass
+    constexpr bool kIntFilter = MODE == kFilter && Tile::kIntScores;
+    int thri[NQ];
+    if constexpr (kIntFilter) {
+#pragma unroll
+        for (int t = 0; t < NQ; ++t)
+            thri[t] = (int)fminf(fmaxf(ceilf(thr[t]), -16777216.0f), 16777216.0f);
+    }
     auto compute_group = [&](const Frag (&xg)[PF], int gbase) {
 #pragma unroll
         for (int j = 0; j < PF; ++j) {
             const int blk = gbase + j * NS;
             if (blk >= blk1) break;
+            if constexpr (kIntFilter) {
+                v16i ai[NQ];
+#pragma unroll
+                for (int t = 0; t < NQ; ++t) ai[t] = Tile::mma_i(xg[j], qf[t]);
+                const int eblk = blk * R;
+                if (blk >= full_blocks) {
+#pragma unroll
+                    for (int t = 0; t < NQ; ++t)
+#pragma unroll
+                        for (int v = 0; v < NA; ++v)
+                            if (eblk + Tile::out_row(lane, v) >= A.n) ai[t][v] = INT_MIN;
+                }
+                int mi[NQ];
+                bool any = false;
+#pragma unroll
+                for (int t = 0; t < NQ; ++t) {
+                    int m = ai[t][0];
+#pragma unroll
+                    for (int v = 1; v < NA; ++v) m = max(m, ai[t][v]);
+                    mi[t] = m;
+                    any = any || (m >= thri[t]);
+                }
+                if (__ballot(any)) {
+#pragma unroll
+                    for (int t = 0; t < NQ; ++t)
+                        if (__ballot(mi[t] >= thri[t]))
+                            emit_pairs<Tile, false, Direct>(A, eb, ai[t], thri[t], qid[t], eblk);
+                }
+                continue;
+            }
             Acc acc[NQ];
 #pragma unroll
             for (int t = 0; t < NQ; ++t) acc[t] = Tile::mma(xg[j], qf[t]);
@@ -833,10 +887,11 @@ inline Plan make_plan(int64_t n, int64_t q, int cfg, int chunk_blocks, int rows,
         want = std::min(std::max(want, min_chunks), max_chunks);
         chunk_blocks = (int32_t)((p.n_blocks + want - 1) / want);
     }
-    // a chunk is addressed through one buffer descriptor: below 2^31 bytes
-    // for rows of up to 128 float32 values
+    // a chunk is addressed through one buffer descriptor with 32-bit offsets:
+    // at most 2^30 bytes for rows of up to 128 float32 values, which leaves
+    // room for the prefetch past its end
     const int32_t max_chunk =
-        ((int32_t)(((int64_t)1 << 31) / ((int64_t)rows * 512)) - 1) / kArgSpan * kArgSpan;
+        (int32_t)(((int64_t)1 << 30) / ((int64_t)rows * 512)) / kArgSpan * kArgSpan;
     // whole argmax spans per chunk, so a winning lane group lies in one chunk
     chunk_blocks = (chunk_blocks + kArgSpan - 1) / kArgSpan * kArgSpan;
     chunk_blocks = std::min(chunk_blocks, max_chunk);
