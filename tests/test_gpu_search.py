@@ -509,3 +509,43 @@ def test_filter_lower_minus_inf_ragged(hn):
         assert c_all == 5 * 1001
         assert int(pairs[:, 1].max()) == 1000
     ix.close()
+
+
+def test_concurrent_streams_and_threads(hn):
+    """One index searched from three host threads at once, each on its own
+    stream and precision (per-stream scratch): every result equals the
+    single-stream search."""
+    import threading
+
+    import torch
+    w = hn_inputs.workload(1)
+    db = w.db()
+    qs = w.queries(db)
+    ix = hn.Index(dev(db), w.k, w.alpha)
+    dq = dev(qs)
+    ref_i, ref_s = ix.search(dq)
+    torch.cuda.synchronize()
+    precs = ("fp32", "bf16", "int8")
+    streams = [torch.cuda.Stream() for _ in precs]
+    results, errors = [None] * len(precs), []
+
+    def work(t):
+        try:
+            with torch.cuda.stream(streams[t]):
+                outs = [ix.search(dq, precision=precs[t]) for _ in range(4)]
+            streams[t].synchronize()
+            results[t] = outs
+        except Exception as e:  # reported below
+            errors.append(e)
+
+    say("3 threads x 4 searches on 3 streams")
+    threads = [threading.Thread(target=work, args=(t,)) for t in range(len(precs))]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    for t in range(len(precs)):
+        for i, s in results[t]:
+            assert torch.equal(i, ref_i) and torch.equal(s, ref_s), precs[t]
+    ix.close()
