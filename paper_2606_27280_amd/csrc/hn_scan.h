@@ -593,8 +593,10 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
             }
             float mx[NQ];
             if constexpr (MODE != kArgmax) {
+                // from -inf: the tree is max3 operations only (no separate
+                // quieting of the first scores)
 #pragma unroll
-                for (int t = 0; t < NQ; ++t) mx[t] = acc_max<Acc, NA>(acc[t]);
+                for (int t = 0; t < NQ; ++t) mx[t] = acc_max_from<Acc, NA>(-INFINITY, acc[t]);
             }
             if constexpr (MODE == kArgmax) {
                 const int sp = blk / kArgSpan;
