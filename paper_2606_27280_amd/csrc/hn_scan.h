@@ -60,6 +60,17 @@ struct ScanArgs {
     const float *init_best;  // window: starting running maximum per query, or NULL
     int32_t q_base;     // added to the query of every emitted pair (several
                         // databases sharing one pair list and flag array)
+    // filter: rescoring fused into the flush (psim != NULL).  Each stored
+    // pair gets its canonical float64 sim in psim and raises best_key of its
+    // query; with rs_major32 the float32 major dot is re-checked against
+    // rs_thr32 first (-inf when it fails, as the separate rescoring does).
+    double *psim;
+    unsigned long long *best_key;
+    int32_t *cnt;           // survivor counts per query, or NULL
+    const float *rs_queries, *rs_rows;  // float32 [q][128], [n][128]
+    const float *rs_major32;            // re-check stream [n_pad][rs_kp], or NULL
+    const float *rs_thr32;
+    int32_t rs_kp, rs_k;
 };
 
 // ------------------------------------------------------------ tile shapes
@@ -68,6 +79,7 @@ struct ScanArgs {
 struct Shape16 {
     static constexpr int kRows = 16, kCols = 16, kGroups = 4, kAcc = 4;
     static constexpr bool kIntScores = false;  // exact integer sums (mma_i)
+    static constexpr bool kFused = false;      // filter flush may rescore (psim)
     typedef v4f Acc;
     __device__ __forceinline__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
@@ -75,6 +87,7 @@ struct Shape16 {
 struct Shape32 {
     static constexpr int kRows = 32, kCols = 32, kGroups = 2, kAcc = 16;
     static constexpr bool kIntScores = false;  // exact integer sums (mma_i)
+    static constexpr bool kFused = false;      // filter flush may rescore (psim)
     typedef v16f Acc;
     __device__ __forceinline__ static int out_row(int lane, int v) {
         return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -186,6 +199,7 @@ struct BF16Tile : Shape16 {
     static constexpr int kFragRegs = kSlice / 2;
     typedef Regs<kFragRegs> Frag;
     HN_SAME_Q_OPERAND
+    static constexpr bool kFused = true;  // the bf16 and int8 filters rescore in their flushes
     __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
         Acc acc = {0.0f, 0.0f, 0.0f, 0.0f};
         if constexpr (kSlice == 4) {
@@ -215,6 +229,7 @@ struct BF16Tile32 : Shape32 {
     static constexpr int kFragRegs = kSlice / 2;
     typedef Regs<kFragRegs> Frag;
     HN_SAME_Q_OPERAND
+    static constexpr bool kFused = true;  // the bf16 and int8 filters rescore in their flushes
     __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
         Acc acc = {};
 #pragma unroll
@@ -289,6 +304,7 @@ struct I8Tile32 : Shape32 {
     static constexpr int kFragRegs = kSlice / 4;
     typedef Regs<kFragRegs> Frag;
     HN_SAME_Q_OPERAND
+    static constexpr bool kFused = true;  // the bf16 and int8 filters rescore in their flushes
     // The filter compares these exact int32 sums with integer thresholds; the
     // other modes take them as float32 (exact: |sum| < 2^24).
     static constexpr bool kIntScores = true;
@@ -365,7 +381,7 @@ struct EmitBuf {
     bool full;    // wave-uniform: a pair did not fit (non-direct mode)
 };
 
-template <bool WithVal>
+template <bool WithVal, bool Fused>
 __device__ __forceinline__ void flush_pairs(const ScanArgs &A, EmitBuf &B) {
     if (B.count == 0) return;
     __builtin_amdgcn_wave_barrier();
@@ -378,6 +394,30 @@ __device__ __forceinline__ void flush_pairs(const ScanArgs &A, EmitBuf &B) {
         if ((int64_t)pos < A.cap) {
             A.pairs[pos] = pr;
             if (WithVal) A.pair_val[pos] = B.vals[i];
+            if (Fused && !WithVal && A.psim) {
+                const float *qv = A.rs_queries + (int64_t)pr.x * kDim;
+                bool keep = true;
+                if (A.rs_major32) {
+                    const float *xm = A.rs_major32 + (int64_t)pr.y * A.rs_kp;
+                    float sm = 0.0f;
+                    for (int j = 0; j < A.rs_k; j += 4) {
+                        const float4 x4 = *reinterpret_cast<const float4 *>(xm + j);
+                        const float4 q4 = *reinterpret_cast<const float4 *>(qv + j);
+                        sm = fmaf(q4.x, x4.x, sm);
+                        sm = fmaf(q4.y, x4.y, sm);
+                        sm = fmaf(q4.z, x4.z, sm);
+                        sm = fmaf(q4.w, x4.w, sm);
+                    }
+                    keep = sm >= A.rs_thr32[pr.x];
+                }
+                double sv = -INFINITY;
+                if (keep) {
+                    sv = sim64(qv, A.rs_rows + (int64_t)pr.y * kDim);
+                    atomicMax(&A.best_key[pr.x], key_of(sv));
+                }
+                A.psim[pos] = sv;
+                if (A.cnt) atomicAdd(&A.cnt[pr.x], 1);
+            }
         } else {
             A.qflag[pr.x] = 1;
         }
@@ -413,7 +453,7 @@ __device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B, const 
         if (total == 0) continue;
         if (B.count + total > kEmitCap) {
             if constexpr (Direct) {
-                flush_pairs<WithVal>(A, B);
+                flush_pairs<WithVal, Tile::kFused>(A, B);
             } else {
                 B.full = true;
                 return;
@@ -666,7 +706,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
 
     if constexpr (MODE == kFilter || MODE == kWindow) {
         if constexpr (Direct) {
-            flush_pairs<MODE == kWindow>(A, eb);
+            flush_pairs<MODE == kWindow, Tile::kFused>(A, eb);
         } else {
             // flush only if no wave of the item overflowed; else re-run it.
             // The decision is made uniform explicitly: a branch the compiler
@@ -677,7 +717,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
             const bool redo =
                 __builtin_amdgcn_readfirstlane(sh_full[0] | sh_full[1] | sh_full[2] | sh_full[3]) != 0;
             if (!redo) {
-                flush_pairs<MODE == kWindow>(A, eb);
+                flush_pairs<MODE == kWindow, Tile::kFused>(A, eb);
             } else if (threadIdx.x == 0) {
                 A.redo[atomicAdd(A.redo_count, 1u)] = redo_id;
             }

@@ -398,6 +398,8 @@ int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *o
     int rc = stage_seed(ix, queries, q, o, lower_in, lower_idx_in, cap, W, s, single);
     if (rc) return rc;
     ScanArgs A = filter_args(ix, W, q, W.pairs, cap);
+    // must match the tiles compiled with kFused (every bf16 and int8 tile)
+    const bool fused = W.precision == HN_PREC_BF16 || W.precision == HN_PREC_INT8;
     if (single) {
         A.thr = W.win_scan;
         A.init_best = W.init_best;
@@ -408,6 +410,25 @@ int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *o
         ProfScope prof_(s, "win_threshold");
         hipLaunchKernelGGL(win_threshold, dim3(blocks_for(q, 4)), dim3(256), 0, s, W.part_val,
                            W.plan.n_chunks, (int32_t)W.plan.q_pad, q, W.win, W.thr, W.thr_ref);
+    } else if (fused) {
+        // bf16 and int8: rescoring fused into the filter's flushes (the scan
+        // is bound by its epilogue and leaves HBM idle, so the row gathers of
+        // the survivors ride along).  Float32 keeps its pass purely on the
+        // matrix cores, fp8 (thousands of re-check rejects per query) keeps
+        // the separate re-check.
+        A.psim = W.psim;
+        A.best_key = W.best_key;
+        A.cnt = ((aux && aux->survivors) || stats) ? W.cnt : nullptr;
+        A.rs_queries = queries;
+        A.rs_rows = ix->rows;
+        if (W.precision != HN_PREC_FP32) {
+            A.rs_major32 = ix->major32;
+            A.rs_thr32 = W.thr32;
+            A.rs_kp = ix->kp;
+            A.rs_k = ix->k;
+        }
+        rc = launch_scan<kFilter>(W.precision, W.width, W.cfg, W.plan, A, s);
+        if (rc) return rc;
     } else {
         rc = launch_scan<kFilter>(W.precision, W.width, W.cfg, W.plan, A, s);
         if (rc) return rc;
@@ -438,10 +459,10 @@ int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *o
         R.thr32 = W.thr_ref;
         ProfScope prof_(s, "rescore_window");
         hipLaunchKernelGGL(rescore_kernel<2>, dim3(rgrid), dim3(256), 0, s, R);
-    } else if (W.precision == HN_PREC_FP32) {
+    } else if (!fused && W.precision == HN_PREC_FP32) {
         ProfScope prof_(s, "rescore");
         hipLaunchKernelGGL(rescore_kernel<0>, dim3(rgrid), dim3(256), 0, s, R);
-    } else {
+    } else if (!fused) {
         ProfScope prof_(s, "rescore_recheck");
         hipLaunchKernelGGL(rescore_kernel<1>, dim3(rgrid), dim3(256), 0, s, R);
     }
