@@ -370,12 +370,59 @@ def test_filter_survivor_sets_match_oracle(hn):
         may = set(oracle.survivor_list(db, qs[qi], w.k, w.alpha,
                                        L[qi] - 2 * slack[qi] - 2.0 ** -20).tolist())
         assert must <= got <= may, qi
+    # the low-precision filters against the same sets, within their own slack
+    for prec in ("bf16", "fp8", "int8"):
+        say("filter survivors: %s" % prec)
+        pp, pc, ps = ix.filter_survivors(dev(qs), dev(L), cap=1 << 20, precision=prec)
+        pp, ps = pp[:pc].cpu().numpy(), ps.cpu().numpy()
+        for qi in range(len(qs)):
+            got = set(pp[pp[:, 0] == qi, 1].tolist())
+            must = set(oracle.survivor_list(db, qs[qi], w.k, w.alpha, L[qi] + 2.0 ** -40).tolist())
+            may = set(oracle.survivor_list(db, qs[qi], w.k, w.alpha,
+                                           L[qi] - 2 * ps[qi] - 2.0 ** -20).tolist())
+            assert must <= got <= may, (prec, qi)
     # a lower bound of -inf keeps everything; +inf keeps nothing
     lo = torch.full((3,), -math.inf, dtype=torch.float64, device="cuda:0")
     _, c_all, _ = ix.filter_survivors(dev(qs[:3]), lo, cap=0)
     assert c_all == 3 * len(db)
     _, c_none, _ = ix.filter_survivors(dev(qs[:3]), -lo, cap=0)
     assert c_none == 0
+    for prec in ("bf16", "fp8", "int8"):
+        _, c_all, _ = ix.filter_survivors(dev(qs[:3]), lo, cap=0, precision=prec)
+        assert c_all == 3 * len(db), prec
+        _, c_none, _ = ix.filter_survivors(dev(qs[:3]), -lo, cap=0, precision=prec)
+        assert c_none == 0, prec
+    ix.close()
+
+
+def test_int8_filter_equals_thresholded_scores(hn):
+    """The int8 filter compares exact integer sums with integer thresholds;
+    its pairs are exactly the entries whose int8 scan score (from the score
+    buffer, the same sums as float32) reaches the search's threshold."""
+    w = hn_inputs.workload(1)
+    db = w.db()
+    qs = w.queries(db)[:40]
+    ix = hn.Index(dev(db), w.k, w.alpha)
+    say("int8 filter vs thresholded int8 scan scores: 40 queries")
+    _, _, aux = ix.search(dev(qs), aux=True, precision="int8")
+    L = aux["seed_sim"]
+    thr = aux["threshold"].cpu().numpy()  # in int8 scan units
+    scores = ix.scan_scores(dev(qs), precision="int8").cpu().numpy()
+    pp, pc, _ = ix.filter_survivors(dev(qs), L, cap=1 << 20, precision="int8")
+    pp = pp[:pc].cpu().numpy()
+    def scale(v):  # the power-of-two int8 scale 2^(e-7) of max |v[:k]| = f 2^e
+        return np.ldexp(1.0, np.frexp(np.float32(np.abs(v[..., :w.k]).max()))[1] - 7)
+
+    sx = scale(db)
+    n_checked = 0
+    for qi in range(len(qs)):
+        # the score buffer holds the sums times s_q s_x (powers of two: exact)
+        units = scores[qi].astype(np.float64) / (scale(qs[qi]) * sx)
+        got = set(pp[pp[:, 0] == qi, 1].tolist())
+        want = set(np.nonzero(units >= thr[qi])[0].tolist())
+        assert got == want, qi
+        n_checked += len(want)
+    assert n_checked > 0
     ix.close()
 
 
