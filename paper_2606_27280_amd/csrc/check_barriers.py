@@ -3,50 +3,86 @@ compiler structured as divergent (a loop exit accumulating an exec mask,
 `s_andn2_b64 exec, exec, ...`) may contain a work-group barrier.  In such a
 loop waves can reach the barrier a different number of times, which
 deadlocks the work-group.  Usage: check_barriers.py file.s [--verbose];
-exit status 1 when a loop is flagged."""
+exit status 1 when a loop is flagged.
+
+Loop structure comes from the compiler's block annotations ("This Loop
+Header", "in Loop: Header=", "Parent Loop"), which sit on the label line or
+on the comment-only lines that follow it.  The block holding a loop's exec
+exit can be laid out outside the loop's annotated blocks (before its header),
+so an exec-mask exit also marks the loops whose headers it branches or falls
+through to."""
 import re, sys
 from collections import defaultdict
-asm = open(sys.argv[1]).read().split('\n')
-starts = [i for i, l in enumerate(asm) if re.match(r'^_Z\S+:', l)]
-flag = 0; total = 0; flagged_syms = []
-for si in starts:
-    sym = asm[si].split(':')[0]
-    end = next(i for i in range(si + 1, len(asm)) if asm[i].startswith('.Lfunc_end'))
-    body = asm[si:end]
-    total += 1
-    parents = {}          # header -> list of parent headers
-    cur_loops = []        # loops of the current block
-    loop_has_bar = defaultdict(bool); loop_div = defaultdict(bool)
-    i = 0
-    while i < len(body):
-        l = body[i]
-        m = re.match(r'^(?:\.L(BB\d+_\d+)|; %bb\.\d+):', l)
-        if m:
-            hm = re.search(r'Header=(BB\d+_\d+)', l)
-            if 'This Loop Header' in l or 'This Inner Loop Header' in l:
+
+LABEL = re.compile(r'^(?:\.L(BB\d+_\d+)|; %bb\.(\d+)):')
+
+
+def annotation(body, i):
+    """The label line's comment plus the comment-only lines after it."""
+    text = [body[i]]
+    k = i + 1
+    while k < len(body) and body[k].strip().startswith(';') and not LABEL.match(body[k]):
+        text.append(body[k])
+        k += 1
+    return ' '.join(text)
+
+
+def check(asm, verbose=False):
+    starts = [i for i, l in enumerate(asm) if re.match(r'^_Z\S+:', l)]
+    flagged = []
+    for si in starts:
+        sym = asm[si].split(':')[0]
+        end = next(i for i in range(si + 1, len(asm)) if asm[i].startswith('.Lfunc_end'))
+        body = asm[si:end]
+        parents = {}          # loop header -> enclosing loop headers
+        cur_loops = []        # loops of the current block, innermost first
+        has_bar = defaultdict(bool)
+        div = defaultdict(bool)
+        exits = []            # labels reached from an exec-mask exit
+        for i, l in enumerate(body):
+            m = LABEL.match(l)
+            if m:
                 name = m.group(1)
-                ps = []
-                k = i - 1
-                while k >= 0 and body[k].strip().startswith(';') and 'Parent Loop' in body[k]:
-                    ps.append(re.search(r'Parent Loop (BB\d+_\d+)', body[k]).group(1)); k -= 1
-                # parents may also be listed on following comment lines
-                parents[name] = ps
-                cur = [name] + ps
-            elif hm:
-                h = hm.group(1)
-                cur = [h] + parents.get(h, [])
-            else:
-                cur = []
-            cur_loops = cur
-        t = l.strip()
-        if t.startswith('s_barrier'):
-            for h in cur_loops: loop_has_bar[h] = True
-        if 's_andn2_b64 exec, exec' in t:
-            for h in cur_loops[:1]: loop_div[h] = True
-        i += 1
-    for h in loop_div:
-        if loop_has_bar[h]:
-            flag += 1; flagged_syms.append(sym)
-            if len(sys.argv) > 2: print('DIVERGENT LOOP WITH BARRIER', sym[:100], h)
-print('kernels checked', total, 'flagged loops', flag, 'kernels', len(set(flagged_syms)))
-sys.exit(1 if flag else 0)
+                ann = annotation(body, i)
+                ps = re.findall(r'Parent Loop (BB\d+_\d+)', ann)
+                if name and re.search(r'This (?:Inner )?Loop Header', ann):
+                    # innermost enclosing loop first
+                    parents[name] = sorted(set(ps), key=lambda h: -ps.index(h))
+                    cur_loops = [name] + parents[name]
+                else:
+                    hm = re.search(r'in Loop: Header=(BB\d+_\d+)', ann)
+                    cur_loops = ([hm.group(1)] + parents.get(hm.group(1), [])) if hm else []
+            t = l.strip()
+            if t.startswith('s_barrier'):
+                for h in cur_loops:
+                    has_bar[h] = True
+            if 's_andn2_b64 exec, exec' in t:
+                for h in cur_loops[:1]:
+                    div[h] = True
+                k = i + 1
+                while k < len(body) and not LABEL.match(body[k]):
+                    bm = re.match(r'\s*s_cbranch_exec(?:nz|z)\s+\.L(BB\d+_\d+)', body[k])
+                    if bm:
+                        exits.append(bm.group(1))
+                    k += 1
+                if k < len(body):
+                    fm = LABEL.match(body[k])
+                    if fm and fm.group(1):
+                        exits.append(fm.group(1))
+        for h in exits:
+            if h in parents:
+                div[h] = True
+        for h in div:
+            if has_bar[h]:
+                flagged.append((sym, h))
+                if verbose:
+                    print('DIVERGENT LOOP WITH BARRIER', sym[:100], h)
+    return len(starts), flagged
+
+
+if __name__ == '__main__':
+    asm = open(sys.argv[1]).read().split('\n')
+    total, flagged = check(asm, len(sys.argv) > 2)
+    print('kernels checked', total, 'flagged loops', len(flagged), 'kernels',
+          len(set(s for s, _ in flagged)))
+    sys.exit(1 if flagged else 0)

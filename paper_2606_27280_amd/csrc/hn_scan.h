@@ -57,6 +57,7 @@ struct ScanArgs {
     float *scores;      // store: [q_count][n]
     int *redo;          // items to re-run (capacity n_items)
     unsigned *redo_count;  // zero before the launch
+    unsigned *item_ctr;    // kXcds item counters, zero before the launch; NULL: static order
     const float *init_best;  // window: starting running maximum per query, or NULL
     int32_t q_base;     // added to the query of every emitted pair (several
                         // databases sharing one pair list and flag array)
@@ -799,6 +800,29 @@ __global__ __launch_bounds__(256) HN_SCAN_ATTR void scan_kernel(ScanArgs A) {
     const int x = (int)(blockIdx.x % kXcds), w = (int)(blockIdx.x / kXcds);
     const int per = (A.n_items + kXcds - 1) / kXcds;
     const int lo = x * per, hi = min(A.n_items, lo + per);
+    if (A.item_ctr) {
+        // Dynamic order: the XCD's groups take its items in list order from
+        // a counter, so items whose survivors cost more (queries with weak
+        // lower bounds) do not pile up on the groups a static stride would
+        // give them to.  Wave 0 claims the next item (every lane adds, lane 0
+        // adds 1, so lane 0's old value is the claim whether or not the
+        // lanes' atomics are combined) and shares it through LDS.  No branch
+        // in the loop depends on the lane: the loop stays uniform, and every
+        // wave reaches the barriers inside it the same number of times.
+        __shared__ int sh_item;
+        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+        const unsigned add = (threadIdx.x & 63) == 0 ? 1u : 0u;
+        for (;;) {
+            if (wave == 0)
+                sh_item = lo + (int)__builtin_amdgcn_readfirstlane(atomicAdd(A.item_ctr + x, add));
+            __syncthreads();
+            const int item = __builtin_amdgcn_readfirstlane(sh_item);
+            __syncthreads();
+            if (item >= hi) break;
+            scan_item<Tile, NQ, WQ, MODE, false>(A, item, item, sh_val, sh_idx, sh_full, eb);
+        }
+        return;
+    }
     for (int item = lo + w; item < hi; item += groups_per_xcd)
         scan_item<Tile, NQ, WQ, MODE, false>(A, item, item, sh_val, sh_idx, sh_full, eb);
 }

@@ -305,6 +305,9 @@ ScanArgs filter_args(const hn_index *ix, const Work &W, int64_t q, int2 *pairs, 
     A.qflag = W.qflag;
     A.redo = W.redo;
     A.redo_count = W.work + 2 * kXcds + 1;
+    // dynamic item order only where items differ in cost: with one query
+    // block every item holds the same queries and the static order is even
+    A.item_ctr = p.n_qb > 1 ? W.work + kXcds : nullptr;
     return A;
 }
 
@@ -940,6 +943,7 @@ extern "C" int hn_bruteforce_top1(const float *db, int64_t n, int32_t d, const f
     A.cap = cap;
     A.redo = redo;
     A.redo_count = work + 2 * kXcds + 1;
+    A.item_ctr = p.n_qb > 1 ? work + kXcds : nullptr;
     rc = launch_scan<kWindow>(HN_PREC_FP32, kDim, cfg, p, A, s);
     if (rc) return rc;
     {
