@@ -34,10 +34,12 @@ __global__ void copy_in(const float4 *__restrict__ q, const int64_t *__restrict_
 }
 
 __global__ void multi_reset(int32_t *qflag, int64_t total_pad, unsigned *redo_counts,
-                            int n_groups, unsigned long long *counter) {
+                            int n_groups, unsigned *item_ctrs, int n_ctrs,
+                            unsigned long long *counter) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t < total_pad) qflag[t] = 0;
     if (t < n_groups) redo_counts[t] = 0u;
+    if (t < n_ctrs) item_ctrs[t] = 0u;
     if (t < 2) counter[t] = 0ull;
 }
 
@@ -87,6 +89,7 @@ struct hn_multi_plan {
     DbRef *dbref = nullptr;
     int *redo = nullptr;
     unsigned *redo_counts = nullptr;
+    unsigned *item_ctrs = nullptr;  // per group: kXcds item counters of each scan pass
     std::vector<MultiGroup> groups;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -114,8 +117,11 @@ bool multi_width_ok(int precision, int w) {
 int enqueue(hn_multi_plan *P, const float *queries, int64_t *out_idx, double *out_sim,
             hipStream_t s) {
     const int ng = (int)P->groups.size();
-    hipLaunchKernelGGL(multi_reset, dim3(blocks_for(std::max<int64_t>(P->total_pad, 64))),
-                       dim3(256), 0, s, P->qflag, P->total_pad, P->redo_counts, ng, P->counter);
+    const int n_ctrs = 2 * kXcds * ng;
+    const int64_t reset_n = std::max<int64_t>(std::max<int64_t>(P->total_pad, 64), n_ctrs);
+    hipLaunchKernelGGL(multi_reset, dim3(blocks_for(reset_n)),
+                       dim3(256), 0, s, P->qflag, P->total_pad, P->redo_counts, ng, P->item_ctrs,
+                       n_ctrs, P->counter);
     hipLaunchKernelGGL(copy_in, dim3((unsigned)std::min<int64_t>(blocks_for(P->total_q * 32), 8192)),
                        dim3(256), 0, s, reinterpret_cast<const float4 *>(queries), P->o2p,
                        P->total_q, reinterpret_cast<float4 *>(P->q_buf));
@@ -130,7 +136,7 @@ int enqueue(hn_multi_plan *P, const float *queries, int64_t *out_idx, double *ou
         ProfScope prof_(s, "multi_scan_argmax");
         if (launch_scan_multi(P->precision, kArgmax, G.width, G.cfg, P->scan_argmax,
                               P->items + G.item_off, G.n_items, P->redo + G.item_off,
-                              P->redo_counts + g, s))
+                              P->redo_counts + g, P->item_ctrs + (2 * g) * kXcds, s))
             return fail(HN_ERR_INVALID_ARG, "no multi-database scan for width %d", G.width);
     }
     {
@@ -144,7 +150,7 @@ int enqueue(hn_multi_plan *P, const float *queries, int64_t *out_idx, double *ou
         ProfScope prof_(s, "multi_scan_filter");
         if (launch_scan_multi(P->precision, kFilter, G.width, G.cfg, P->scan_filter,
                               P->items + G.item_off, G.n_items, P->redo + G.item_off,
-                              P->redo_counts + g, s))
+                              P->redo_counts + g, P->item_ctrs + (2 * g + 1) * kXcds, s))
             return fail(HN_ERR_INVALID_ARG, "no multi-database scan for width %d", G.width);
     }
     RescoreArgs R;
@@ -328,7 +334,9 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
                  o_pairs = add(cap, sizeof(int2)), o_psim = add(cap, 8),
                  o_items = add(std::max<int64_t>(P->total_items, 1), sizeof(int2)),
                  o_redo = add(std::max<int64_t>(P->total_items, 1), 4),
-                 o_rc = add(P->groups.size() + 1, 4), o_o2p = add(std::max<int64_t>(total_q, 1), 8),
+                 o_rc = add(P->groups.size() + 1, 4),
+                 o_ictr = add(2 * kXcds * P->groups.size() + 1, 4),
+                 o_o2p = add(std::max<int64_t>(total_q, 1), 8),
                  o_sa = add(n_db, sizeof(ScanArgs)), o_sf = add(n_db, sizeof(ScanArgs)),
                  o_seed = add(n_db, sizeof(SeedArgs)), o_prep = add(n_db, sizeof(PrepArgs)),
                  o_db = add(n_db, sizeof(DbRef));
@@ -359,6 +367,7 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
     P->items = reinterpret_cast<int2 *>(m + o_items);
     P->redo = reinterpret_cast<int *>(m + o_redo);
     P->redo_counts = reinterpret_cast<unsigned *>(m + o_rc);
+    P->item_ctrs = reinterpret_cast<unsigned *>(m + o_ictr);
     P->o2p = reinterpret_cast<int64_t *>(m + o_o2p);
     P->scan_argmax = reinterpret_cast<ScanArgs *>(m + o_sa);
     P->scan_filter = reinterpret_cast<ScanArgs *>(m + o_sf);

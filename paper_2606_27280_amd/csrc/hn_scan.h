@@ -804,23 +804,22 @@ __global__ __launch_bounds__(256) HN_SCAN_ATTR void scan_kernel(ScanArgs A) {
         // Dynamic order: the XCD's groups take its items in list order from
         // a counter, so items whose survivors cost more (queries with weak
         // lower bounds) do not pile up on the groups a static stride would
-        // give them to.  Wave 0 claims the next item (every lane adds, lane 0
-        // adds 1, so lane 0's old value is the claim whether or not the
-        // lanes' atomics are combined) and shares it through LDS.  No branch
-        // in the loop depends on the lane: the loop stays uniform, and every
-        // wave reaches the barriers inside it the same number of times.
+        // give them to.  Thread 0 claims the next item and shares it through
+        // LDS; the claim is the loop's condition (before the first item and
+        // after each), which the compiler keeps uniform, so every wave
+        // reaches the barriers inside the loop the same number of times (a
+        // claim at the head of the loop body made it structure the loop as
+        // divergent).
         __shared__ int sh_item;
-        const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-        const unsigned add = (threadIdx.x & 63) == 0 ? 1u : 0u;
-        for (;;) {
-            if (wave == 0)
-                sh_item = lo + (int)__builtin_amdgcn_readfirstlane(atomicAdd(A.item_ctr + x, add));
+        auto claim = [&]() {
+            if (threadIdx.x == 0) sh_item = lo + (int)atomicAdd(A.item_ctr + x, 1u);
             __syncthreads();
-            const int item = __builtin_amdgcn_readfirstlane(sh_item);
+            const int it = __builtin_amdgcn_readfirstlane(sh_item);
             __syncthreads();
-            if (item >= hi) break;
+            return it;
+        };
+        for (int item = claim(); item < hi; item = claim())
             scan_item<Tile, NQ, WQ, MODE, false>(A, item, item, sh_val, sh_idx, sh_full, eb);
-        }
         return;
     }
     for (int item = lo + w; item < hi; item += groups_per_xcd)
@@ -846,19 +845,34 @@ __global__ __launch_bounds__(256) void scan_redo_kernel(ScanArgs A) {
 template <class Tile, int NQ, int WQ, int MODE>
 __global__ __launch_bounds__(256) void scan_multi_kernel(const ScanArgs *__restrict__ dbs,
                                                          const int2 *__restrict__ items,
-                                                         int n_items) {
+                                                         int n_items, unsigned *item_ctr) {
     HN_SCAN_SHARED(Tile, NQ, MODE)
     const int groups_per_xcd = (int)gridDim.x / kXcds;
     const int x = (int)(blockIdx.x % kXcds), w = (int)(blockIdx.x / kXcds);
     const int per = (n_items + kXcds - 1) / kXcds;
     const int lo = x * per, hi = min(n_items, lo + per);
-    for (int item = lo + w; item < hi; item += groups_per_xcd) {
+    auto run = [&](int item) {
         const int2 it = items[item];
         const int d = __builtin_amdgcn_readfirstlane(it.x);
         const int local = __builtin_amdgcn_readfirstlane(it.y);
         const ScanArgs A = dbs[d];
         scan_item<Tile, NQ, WQ, MODE, false>(A, local, item, sh_val, sh_idx, sh_full, eb);
+    };
+    if (item_ctr) {
+        // device work queue: items of databases of very different sizes and
+        // query counts are claimed in list order per XCD (as in scan_kernel)
+        __shared__ int sh_item;
+        auto claim = [&]() {
+            if (threadIdx.x == 0) sh_item = lo + (int)atomicAdd(item_ctr + x, 1u);
+            __syncthreads();
+            const int it = __builtin_amdgcn_readfirstlane(sh_item);
+            __syncthreads();
+            return it;
+        };
+        for (int item = claim(); item < hi; item = claim()) run(item);
+        return;
     }
+    for (int item = lo + w; item < hi; item += groups_per_xcd) run(item);
 }
 
 template <class Tile, int NQ, int WQ, int MODE>
@@ -1087,13 +1101,15 @@ inline unsigned tile_slots(int mode, int cfg) {
 
 // Several databases in one launch (argmax and filter modes).  The grid is
 // sized by the occupancy of the single-database kernel of the same tile.
+// item_ctr: kXcds item counters, zero before the launch (NULL: static order).
 template <class Tile, int MODE, int C>
 inline void launch_multi_one(const ScanArgs *dbs, const int2 *items, int n_items,
-                             const int *redo, const unsigned *redo_count, hipStream_t s) {
+                             const int *redo, const unsigned *redo_count, unsigned *item_ctr,
+                             hipStream_t s) {
     if constexpr (kCfgNQ[C] * tile_cost<Tile>() <= kTileBudget) {
         hipLaunchKernelGGL((scan_multi_kernel<Tile, kCfgNQ[C], kCfgWQ[C], MODE>),
                            dim3(persistent_grid<Tile, kCfgNQ[C], kCfgWQ[C], MODE>(n_items)),
-                           dim3(256), 0, s, dbs, items, n_items);
+                           dim3(256), 0, s, dbs, items, n_items, item_ctr);
         if constexpr (MODE == kFilter)
             hipLaunchKernelGGL((scan_multi_redo_kernel<Tile, kCfgNQ[C], kCfgWQ[C], MODE>),
                                dim3(persistent_grid<Tile, kCfgNQ[C], kCfgWQ[C], MODE>(n_items)),
@@ -1104,15 +1120,17 @@ inline void launch_multi_one(const ScanArgs *dbs, const int2 *items, int n_items
 template <class Tile>
 inline int launch_tile_multi(int mode, int cfg, const ScanArgs *dbs, const int2 *items,
                              int n_items, const int *redo, const unsigned *redo_count,
-                             hipStream_t s) {
+                             unsigned *item_ctr, hipStream_t s) {
     if (cfg < 0 || cfg >= kNumCfg || kCfgNQ[cfg] * tile_cost<Tile>() > kTileBudget) return 1;
     if (mode != kArgmax && mode != kFilter) return 1;
 #define HN_MULTI_CASE(C)                                                   \
     case C:                                                                \
         if (mode == kArgmax)                                                           \
-            launch_multi_one<Tile, kArgmax, C>(dbs, items, n_items, redo, redo_count, s); \
+            launch_multi_one<Tile, kArgmax, C>(dbs, items, n_items, redo, redo_count,   \
+                                               item_ctr, s);                            \
         else                                                                           \
-            launch_multi_one<Tile, kFilter, C>(dbs, items, n_items, redo, redo_count, s); \
+            launch_multi_one<Tile, kFilter, C>(dbs, items, n_items, redo, redo_count,   \
+                                               item_ctr, s);                            \
         return 0;
     switch (cfg) {
         HN_MULTI_CASE(0)
@@ -1164,11 +1182,12 @@ unsigned slots_scan_int8(int mode, int w, int cfg);
 // 32; bf16 and fp8 widths 16, 32.  Nonzero if not compiled.
 int launch_scan_multi(int precision, int mode, int w, int cfg, const ScanArgs *dbs,
                       const int2 *items, int n_items, const int *redo,
-                      const unsigned *redo_count, hipStream_t s);
+                      const unsigned *redo_count, unsigned *item_ctr, hipStream_t s);
 #define HN_MULTI_DECL(name)                                                                    \
     int launch_scan_multi_##name(int mode, int w, int cfg, const ScanArgs *dbs,             \
                                  const int2 *items, int n_items, const int *redo,          \
-                                 const unsigned *redo_count, hipStream_t s);
+                                 const unsigned *redo_count, unsigned *item_ctr,           \
+                                 hipStream_t s);
 HN_MULTI_DECL(f32)   // widths 8, 16, 32
 HN_MULTI_DECL(bf16)  // widths 16, 32
 HN_MULTI_DECL(fp8)   // widths 16, 32

@@ -4,8 +4,10 @@
 
 namespace hn {
 int launch_scan_multi_fp8(int mode, int w, int cfg, const ScanArgs *dbs, const int2 *items,
-                         int n_items, const int *redo, const unsigned *redo_count, hipStream_t s) {
-#define HN_MULTI(Tile) launch_tile_multi<Tile>(mode, cfg, dbs, items, n_items, redo, redo_count, s)
+                         int n_items, const int *redo, const unsigned *redo_count,
+                         unsigned *item_ctr, hipStream_t s) {
+#define HN_MULTI(Tile) \
+    launch_tile_multi<Tile>(mode, cfg, dbs, items, n_items, redo, redo_count, item_ctr, s)
     switch (w) {
         case 16: return HN_MULTI(FP8Tile32<16>);
         case 32: return HN_MULTI(FP8Tile32<32>);
