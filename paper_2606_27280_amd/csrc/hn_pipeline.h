@@ -266,6 +266,9 @@ __device__ __forceinline__ double group_sim(const SeedArgs &S, int gid, int lane
 // winning lane group (the group holds the chunk's largest scan score, so
 // these are the near-best entries of distinct chunks).  -inf if fewer than
 // topk such entries exist.  Chunk r's value sits in lane r % 64, slot r / 64.
+// Per-chunk partials read per step by each lane of a seed wave.
+constexpr int kPartBatch = 8;
+
 __device__ __forceinline__ double topk_lower(const SeedArgs &S, const int64_t i, const int lane,
                                           const float *qv, double q_minor) {
     const int m = min(S.n_chunks, min(2 * S.topk, 256));
@@ -279,12 +282,22 @@ __device__ __forceinline__ double topk_lower(const SeedArgs &S, const int64_t i,
         // the next chunk after (pv, pc) in (score desc, chunk asc) order
         float bv = -INFINITY;
         int bc = -1;
-        for (int c = lane; c < S.n_chunks; c += 64) {
-            const float v = S.part_val[(int64_t)c * S.part_ld + i];
-            const bool after = v < pv || (v == pv && c > pc);
-            if (after && (bc < 0 || v > bv)) {
-                bv = v;
-                bc = c;
+        for (int c0 = lane; c0 < S.n_chunks; c0 += 64 * kPartBatch) {
+            // kPartBatch independent loads in flight, then the selection
+            float v[kPartBatch];
+#pragma unroll
+            for (int u = 0; u < kPartBatch; ++u) {
+                const int c = c0 + 64 * u;
+                v[u] = c < S.n_chunks ? S.part_val[(int64_t)c * S.part_ld + i] : -INFINITY;
+            }
+#pragma unroll
+            for (int u = 0; u < kPartBatch; ++u) {
+                const int c = c0 + 64 * u;
+                const bool after = v[u] < pv || (v[u] == pv && c > pc);
+                if (c < S.n_chunks && after && (bc < 0 || v[u] > bv)) {
+                    bv = v[u];
+                    bc = c;
+                }
             }
         }
         for (int o = 32; o > 0; o >>= 1) {
@@ -382,9 +395,21 @@ __device__ __forceinline__ void seed_one(const SeedArgs &S, const int64_t i, con
     } else {
         float bv = -INFINITY;
         int bi = -1;
-        for (int c = lane; c < S.n_chunks; c += 64)
-            lex_merge(bv, bi, S.part_val[(int64_t)c * S.part_ld + i],
-                      S.part_idx[(int64_t)c * S.part_ld + i]);
+        // the query's per-chunk partials, kPartBatch independent loads in
+        // flight per lane (the merge is a lexicographic maximum: any order)
+        for (int c0 = lane; c0 < S.n_chunks; c0 += 64 * kPartBatch) {
+            float v[kPartBatch];
+            int x[kPartBatch];
+#pragma unroll
+            for (int u = 0; u < kPartBatch; ++u) {
+                const int c = c0 + 64 * u;
+                const bool ok = c < S.n_chunks;
+                v[u] = ok ? S.part_val[(int64_t)c * S.part_ld + i] : -INFINITY;
+                x[u] = ok ? S.part_idx[(int64_t)c * S.part_ld + i] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kPartBatch; ++u) lex_merge(bv, bi, v[u], x[u]);
+        }
         for (int o = 32; o > 0; o >>= 1) {
             const float ov = __shfl_xor(bv, o);
             const int oi = __shfl_xor(bi, o);

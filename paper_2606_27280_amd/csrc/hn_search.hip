@@ -105,8 +105,13 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     if (W.cfg < 0)
         return fail(HN_ERR_INVALID_ARG, "query_tiles=%d is not available for this width",
                     o.query_tiles);
-    W.plan = make_plan(ix->n, q, W.cfg, o.chunk_blocks, ti.rows, ti.cols, 8192,
-                       scan_slots(W.precision, window ? kWindow : kFilter, W.width, W.cfg));
+    // With one query block every item holds the same queries and costs the
+    // same: two rounds of the persistent grid (fewer, longer items, less
+    // per-item start-up against the stream) instead of about 8192 items.
+    const int64_t fslots = scan_slots(W.precision, window ? kWindow : kFilter, W.width, W.cfg);
+    const int64_t one_qb = (int64_t)kCfgNQ[W.cfg] * kCfgWQ[W.cfg] * ti.cols;
+    W.plan = make_plan(ix->n, q, W.cfg, o.chunk_blocks, ti.rows, ti.cols,
+                       q <= one_qb && fslots >= kXcds ? 2 * fslots : 8192, fslots);
     const Plan &p = W.plan;
     // The argmax (seed) scan runs on the bf16 copy whatever the filter's
     // precision: the seed only has to be a real entry with a near-maximal
@@ -117,9 +122,14 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     if (W.seed_cfg < 0)
         return fail(HN_ERR_INVALID_ARG, "query_tiles=%d is not available for this width",
                     o.query_tiles);
-    // top-k seeds take the best of up to 2 topk chunks: plan at least that many
-    W.seed_plan = make_plan(ix->n, q, W.seed_cfg, o.chunk_blocks, tis.rows, tis.cols, 8192,
-                            scan_slots(HN_PREC_BF16, kArgmax, ix->kb, W.seed_cfg),
+    // top-k seeds take the best of up to 2 topk chunks: plan at least that many.
+    // One query block: two rounds of the grid as for the filter plan, which
+    // also shortens the seed kernel's walk over the per-chunk partials (one
+    // per chunk and query).
+    const int64_t sslots = scan_slots(HN_PREC_BF16, kArgmax, ix->kb, W.seed_cfg);
+    const int64_t one_sqb = (int64_t)kCfgNQ[W.seed_cfg] * kCfgWQ[W.seed_cfg] * tis.cols;
+    W.seed_plan = make_plan(ix->n, q, W.seed_cfg, o.chunk_blocks, tis.rows, tis.cols,
+                            q <= one_sqb && sslots >= kXcds ? 2 * sslots : 8192, sslots,
                             topk > 1 ? 2 * (int64_t)topk : 1);
     W.shape = tis.rows;
     const Plan &sp = W.seed_plan;
