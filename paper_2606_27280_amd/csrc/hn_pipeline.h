@@ -278,18 +278,25 @@ __device__ __forceinline__ double topk_lower(const SeedArgs &S, const int64_t i,
     float pv = INFINITY;
     int pc = -1;
     int found = 0;  // chunks with a real entry
+    // The partials are read kPartBatch per lane at a time (independent loads
+    // in flight together); with at most 64 x kPartBatch chunks they are read
+    // once and stay in registers for all the rounds.
+    float v[kPartBatch];
+    auto load = [&](int c0) {
+#pragma unroll
+        for (int u = 0; u < kPartBatch; ++u) {
+            const int c = c0 + 64 * u;
+            v[u] = c < S.n_chunks ? S.part_val[(int64_t)c * S.part_ld + i] : -INFINITY;
+        }
+    };
+    const bool resident = S.n_chunks <= 64 * kPartBatch;
+    if (resident) load(lane);
     for (int r = 0; r < m; ++r) {
         // the next chunk after (pv, pc) in (score desc, chunk asc) order
         float bv = -INFINITY;
         int bc = -1;
         for (int c0 = lane; c0 < S.n_chunks; c0 += 64 * kPartBatch) {
-            // kPartBatch independent loads in flight, then the selection
-            float v[kPartBatch];
-#pragma unroll
-            for (int u = 0; u < kPartBatch; ++u) {
-                const int c = c0 + 64 * u;
-                v[u] = c < S.n_chunks ? S.part_val[(int64_t)c * S.part_ld + i] : -INFINITY;
-            }
+            if (!resident) load(c0);
 #pragma unroll
             for (int u = 0; u < kPartBatch; ++u) {
                 const int c = c0 + 64 * u;
@@ -818,18 +825,23 @@ __global__ __launch_bounds__(1024) void prefix_counts(const int32_t *__restrict_
     if (threadIdx.x == 0) off[q] = carry;
 }
 
-// Bucket the rescored pairs by query (order inside a bucket is arbitrary).
+// Bucket the rescored pairs by query: each pair's float64 sim and entry go
+// to its query's contiguous bucket (order inside a bucket is arbitrary).
 __global__ __launch_bounds__(256) void scatter_pairs(const int2 *__restrict__ pairs,
+                                                     const double *__restrict__ psim,
                                                      const unsigned long long *counter, int64_t cap,
                                                      const int64_t *__restrict__ off,
                                                      int32_t *__restrict__ fill,
-                                                     int32_t *__restrict__ seg) {
+                                                     double *__restrict__ bsim,
+                                                     int32_t *__restrict__ bent) {
     const unsigned long long c = *counter;
     const int64_t m = (int64_t)c < cap ? (int64_t)c : cap;
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < m;
          p += (int64_t)gridDim.x * 256) {
-        const int q = pairs[p].x;
-        seg[off[q] + atomicAdd(&fill[q], 1)] = (int32_t)p;
+        const int2 pr = pairs[p];
+        const int64_t j = off[pr.x] + atomicAdd(&fill[pr.x], 1);
+        bsim[j] = psim[p];
+        bent[j] = pr.y;
     }
 }
 
@@ -838,10 +850,14 @@ __global__ __launch_bounds__(256) void scatter_pairs(const int2 *__restrict__ pa
 // (the order is total, so the result does not depend on the bucket order).
 // Missing places (fewer entries than topk) get index -1 and sim -inf; a query
 // with a non-finite component gets -1 and NaN.
+// Pairs per lane that topk_select holds in registers: a bucket of at most
+// 64 x kSelRegs pairs is gathered once; a larger one is re-read per sweep in
+// chunks of that size.
+constexpr int kSelRegs = 16;
+
 __global__ __launch_bounds__(256) void topk_select(const int64_t *__restrict__ off,
-                                                   const int32_t *__restrict__ seg,
-                                                   const int2 *__restrict__ pairs,
-                                                   const double *__restrict__ psim, int64_t q,
+                                                   const double *__restrict__ bsim,
+                                                   const int32_t *__restrict__ bent, int64_t q,
                                                    int topk, const QNorm *__restrict__ qn,
                                                    int64_t *__restrict__ out_idx,
                                                    double *__restrict__ out_sim) {
@@ -853,19 +869,45 @@ __global__ __launch_bounds__(256) void topk_select(const int64_t *__restrict__ o
     double pv = INFINITY;
     int64_t pe = -1;
     bool done = bad;
+    // The bucket (contiguous sims and entries) is read in chunks of 64 x
+    // kSelRegs pairs, all loads of a chunk in flight together, then scanned
+    // in registers.  A bucket of one chunk stays in registers across the
+    // sweeps.
+    double sv[kSelRegs];
+    int ev[kSelRegs];
+    auto gather = [&](int64_t base) {
+#pragma unroll
+        for (int u = 0; u < kSelRegs; ++u) {
+            const int64_t j = base + lane + 64 * u;
+            sv[u] = j < hi ? bsim[j] : -INFINITY;
+            ev[u] = j < hi ? bent[j] : -1;
+        }
+    };
+    // best pair strictly after (pv, pe) in (sim desc, entry asc) order
+    auto scan = [&](double &bv, int64_t &be) {
+#pragma unroll
+        for (int u = 0; u < kSelRegs; ++u) {
+            const double sc = sv[u];
+            const int64_t e = ev[u];
+            const bool after = sc < pv || (sc == pv && e > pe);
+            if (sc != -INFINITY && after && (be < 0 || sc > bv || (sc == bv && e < be))) {
+                bv = sc;
+                be = e;
+            }
+        }
+    };
+    const bool resident = hi - lo <= 64 * kSelRegs;
+    if (resident && !done) gather(lo);
     for (int r = 0; r < topk; ++r) {
         double bv = -INFINITY;
         int64_t be = -1;
         if (!done) {
-            for (int64_t j = lo + lane; j < hi; j += 64) {
-                const int p = seg[j];
-                const double s = psim[p];
-                if (s == -INFINITY) continue;
-                const int64_t e = pairs[p].y;
-                const bool after = s < pv || (s == pv && e > pe);
-                if (after && (be < 0 || s > bv || (s == bv && e < be))) {
-                    bv = s;
-                    be = e;
+            if (resident) {
+                scan(bv, be);
+            } else {
+                for (int64_t base = lo; base < hi; base += 64 * kSelRegs) {
+                    gather(base);
+                    scan(bv, be);
                 }
             }
             for (int o = 32; o > 0; o >>= 1) {

@@ -699,19 +699,26 @@ extern "C" int hn_search_topk(const hn_index *ix, const float *queries, int64_t 
         cap = (int64_t)total;
     }
     Arena *ar = nullptr;
-    rc = arena_for((void *)s, (size_t)(q + 1) * 8 + (size_t)q * 4 + (size_t)cap * 4 + 1024, &ar, 3);
+    rc = arena_for((void *)s, (size_t)(q + 1) * 8 + (size_t)q * 4 + (size_t)cap * 12 + 1024, &ar, 3);
     if (rc) return rc;
     int64_t *off = ar->take<int64_t>(q + 1);
     int32_t *fill = ar->take<int32_t>(q);
-    int32_t *seg = ar->take<int32_t>(cap);
+    double *bsim = ar->take<double>(cap);
+    int32_t *bent = ar->take<int32_t>(cap);
     hipLaunchKernelGGL(fill_i32, dim3(blocks_for(q)), dim3(256), 0, s, fill, q);
     {
-        ProfScope prof_(s, "topk_select");
+        ProfScope prof_(s, "topk_offsets");
         hipLaunchKernelGGL(prefix_counts, dim3(1), dim3(1024), 0, s, W.cnt, q, off);
-        hipLaunchKernelGGL(scatter_pairs, dim3(2048), dim3(256), 0, s, W.pairs, W.counter, cap, off,
-                           fill, seg);
-        hipLaunchKernelGGL(topk_select, dim3(blocks_for(q, 4)), dim3(256), 0, s, off, seg, W.pairs,
-                           W.psim, q, topk, W.qn, out_idx, out_sim);
+    }
+    {
+        ProfScope prof_(s, "topk_scatter");
+        hipLaunchKernelGGL(scatter_pairs, dim3(2048), dim3(256), 0, s, W.pairs, W.psim, W.counter,
+                           cap, off, fill, bsim, bent);
+    }
+    {
+        ProfScope prof_(s, "topk_select");
+        hipLaunchKernelGGL(topk_select, dim3(blocks_for(q, 4)), dim3(256), 0, s, off, bsim, bent,
+                           q, topk, W.qn, out_idx, out_sim);
     }
     HN_HIP(hipGetLastError());
     return HN_OK;

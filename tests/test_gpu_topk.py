@@ -72,6 +72,27 @@ def test_topk_edge_shapes(hn, n, k, alpha, topk):
     ix.close()
 
 
+def test_topk_selection_beyond_register_capacity(hn):
+    # Survivors at the exact k-th best bound are a subset of the top-k
+    # search's survivors; with alpha = 1/4 and 8 clusters some queries keep
+    # more than the 64 x 16 that the selection holds in registers (its memory
+    # path) and others fewer (its register path), in one call.
+    import torch
+    db = hn_inputs.make_db(8192, 8, 1 / 4, 8, 4321)
+    qs = hn_inputs.make_queries(db, 8, 1 / 4, 12, 4, 4322)
+    topk = 20
+    ri, rs = oracle.topk(db, qs, topk)
+    ix = hn.Index(dev(db), 8, 1 / 4)
+    lower = torch.from_numpy(np.ascontiguousarray(rs[:, topk - 1])).to("cuda:0")
+    pairs, count, _ = ix.filter_survivors(dev(qs), lower, cap=len(qs) * 8192)
+    per_q = np.bincount(pairs[:count].cpu().numpy()[:, 0], minlength=len(qs))
+    say("top-%d beyond registers: survivors per query max %d min %d" % (topk, per_q.max(), per_q.min()))
+    assert per_q.max() > 64 * 16
+    idx, sim = ix.search_topk(dev(qs), topk)
+    check(idx, sim, ri, rs, "beyond registers")
+    ix.close()
+
+
 def test_topk_small_list_second_pass_and_errors(hn):
     w = hn_inputs.workload(1)
     db = w.db()
