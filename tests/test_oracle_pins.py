@@ -92,6 +92,41 @@ def test_generator_rows_are_hn_normalised():
             assert (db[:, k:] == 0).all()
 
 
+def test_db_max_norms_exact_integer_rows(orc):
+    """Block-norm maxima on rows built from Pythagorean triples, so every norm
+    is an exact integer and each maximum comes from a different row.  With
+    k = 16: row 0 major (3, 4) = 5, minor 12, full 13; row 1 major (5, 12) =
+    13, minor 0; row 2 major 8, minor 15, full 17; row 3 has 9 at j = 15 (the
+    last major coordinate) and 40 at j = 16 (the first minor one): major 9,
+    minor 40, full 41.  A block boundary off by one, or an inflated norm,
+    changes a result."""
+    k = 16
+    db = np.zeros((4, 128), dtype=np.float32)
+    db[0, 0], db[0, 1], db[0, 16] = 3, 4, 12
+    db[1, 2], db[1, 3] = 5, 12
+    db[2, 5], db[2, 100] = 8, 15
+    db[3, 15], db[3, 16] = 9, 40
+    assert orc.db_max_norms(db, k) == (13.0, 40.0, 41.0)
+    # the same rows split at k = 15 and 17 move row 3's coordinates
+    assert orc.db_max_norms(db, 15) == (13.0, 41.0, 41.0)
+    assert orc.db_max_norms(db, 17) == (41.0, 15.0, 41.0)
+
+
+@pytest.mark.parametrize("k,alpha", [(8, 1 / 32), (16, 1 / 8), (16, 0.0), (64, 0.5)])
+def test_db_max_norms_closed_form_on_hn_rows(orc, k, alpha):
+    """On HN rows the maxima are the closed forms of Eq. 1: sqrt(1 - alpha),
+    sqrt(alpha) and 1, up to the float32 storage of the rows (a relative
+    2^-20), from above and from below."""
+    db = hn_inputs.make_db(2000, k, alpha, 16, 4242 + k)
+    mM, mm, mf = orc.db_max_norms(db, k)
+    tol = 2.0 ** -20
+    for got, want in ((mM, math.sqrt(1 - alpha)), (mm, math.sqrt(alpha)), (mf, 1.0)):
+        if want == 0.0:
+            assert got == 0.0
+        else:
+            assert abs(got / want - 1.0) <= tol, (got, want)
+
+
 # --------------------------------------------------------- bound, Eq. 3
 
 @pytest.mark.parametrize("k,alpha", [(8, 1 / 32), (16, 1 / 8), (4, 1 / 4)])
@@ -342,3 +377,77 @@ def test_literal_bound_fails_on_self_pairs_but_widened_holds(orc):
             over += 1
             assert full > s64 + alpha
     assert over > 0
+
+
+# ------------------------------------------------ soft mode (Section 7)
+
+def _soft_case():
+    """Five entries (d = 4, k = 2) with dyadic values, so every dot product
+    and bound below is exact.  Query q = (1, 0, 1/2, 0), ||q_m|| = 1/2.
+      x0: major (3/8, 0),  minor (0, 1/2)  -> s = 3/8,  sim = 3/8
+      x1: major (5/8, 0),  minor (0, 1/2)  -> s = 5/8,  sim = 5/8  (the seed b)
+      x2: major (1/2, 0),  minor (1/2, 0)  -> s = 1/2,  sim = 3/4  (the NN)
+      x3: major (0, 1),    minor (1/2, 0)  -> s = 0,    sim = 1/4
+      x4: major (7/16, 0), minor (0, 1/2)  -> s = 7/16, sim = 7/16
+    mu_m = 1/2, so ||q_m|| mu_m = alpha = 1/4 and the norm term of the slack
+    is zero; what remains of the slack is below 1e-13."""
+    db = np.array([[0.375, 0, 0, 0.5], [0.625, 0, 0, 0.5], [0.5, 0, 0.5, 0], [0, 1, 0.5, 0],
+                   [0.4375, 0, 0, 0.5]], dtype=np.float32)
+    q = np.array([[1, 0, 0.5, 0]], dtype=np.float32)
+    return db, q
+
+
+@pytest.mark.parametrize("beta,want_idx,want_phase2", [
+    (None, 2, 2),
+    (0.25, 2, 2),
+    (0.125, 2, 1),
+    (0.125 - 2.0 ** -20, 1, 0),
+    (0.0, 1, 0),
+])
+def test_soft_mode_beta_exact_case(orc, beta, want_idx, want_phase2):
+    """Section 7: replacing alpha by beta < alpha in the skip test prunes more
+    and may lose the NN.  Worked by hand on the exact dyadic input above, in
+    Algorithm 1's index order after the seed x1 (best = 5/8):
+      beta = alpha = 1/4: x0's bound 3/8 + 1/4 = 5/8 is not strictly below the
+        best, so x0 is evaluated; x2 (bound 3/4) is evaluated and lifts the
+        best to 3/4; x3 (1/4) and x4 (11/16, above the seed's 5/8 but below
+        the running best 3/4) are skipped: 2 evaluations, result x2;
+      beta = 1/8: x0 (1/2) skipped, x2 (exactly 5/8) evaluated: 1, result x2;
+      beta just below 1/8, or 0: x2's bound falls below 5/8 and nothing is
+        evaluated: the soft mode returns the seed x1."""
+    db, q = _soft_case()
+    r = orc.bnb_top1(db, q, 2, 0.25, beta=beta, threads=1)
+    assert r["seed_idx"][0] == 1 and r["seed_sim"][0] == 0.625
+    assert r["idx"][0] == want_idx
+    assert r["sim"][0] == (0.75 if want_idx == 2 else 0.625)
+    assert r["phase2"][0] == want_phase2
+
+
+@pytest.mark.parametrize("k,alpha", [(8, 1 / 32), (16, 1 / 8)])
+def test_soft_mode_properties_exact(orc, k, alpha):
+    """Properties of Algorithm 1 with beta in the skip test, checked with exact
+    rational dots on small random HN inputs:
+      * the result r is a real entry's sim, at least the seed's and at most the
+        exact best;
+      * every entry whose major dot plus beta reaches r (with a 2^-40 margin
+        for the float64 scores) was compared, so none of them beats r: r is
+        the best over {b} and {i : dot_K + beta >= r};
+      * if the NN's minor dot is at most beta, the NN is found (the weakened
+        bound is still admissible for it)."""
+    db, qs = tiny_hn(60, 12, k, alpha, seed=700 + k, clusters=3)
+    sims = [[exact_dot(q, x) for x in db] for q in qs]
+    majs = [[exact_dot(q, x, 0, k) for x in db] for q in qs]
+    for frac in (0.0, 0.25, 0.5, 0.75, 1.0):
+        beta = frac * alpha
+        r = orc.bnb_top1(db, qs, k, alpha, beta=beta, threads=2)
+        for qi in range(len(qs)):
+            i, v = int(r["idx"][qi]), r["sim"][qi]
+            assert v == orc.sim(qs[qi], db[i])
+            assert v >= r["seed_sim"][qi]
+            best = max(range(len(db)), key=lambda j: (sims[qi][j], -j))
+            assert Fraction(v) <= sims[qi][best] + Fraction(1, 10 ** 12)
+            for j in range(len(db)):
+                if majs[qi][j] + Fraction(beta) >= Fraction(v) + Fraction(2.0 ** -40):
+                    assert sims[qi][j] <= Fraction(v) + Fraction(1, 10 ** 12), (frac, qi, j)
+            if sims[qi][best] - majs[qi][best] <= Fraction(beta):
+                assert i == best or abs(Fraction(v) - sims[qi][best]) < Fraction(1, 10 ** 12)

@@ -112,3 +112,88 @@ def test_hn_backward_matches_finite_differences(orc, k, alpha):
     assert abs((got[:, k:] * f[:, k:]).sum()) < 1e-12
     if alpha == 0.0:
         assert (got[:, k:] == 0).all()
+
+
+def _dyadic_net():
+    """A sparse network whose every pre-activation is a dyadic number of
+    magnitude >= 16 or exactly 0, so every product and sum is exact in
+    float64 and GELU is exact too: erf(z / sqrt 2) rounds to +-1 for
+    |z| >= 16, so GELU(z) = z for z >= 16 and 0 for z <= -16.
+      x[j]      = 1 + j/128
+      W1[u, :]  = one entry: column u mod 128 (u < 128) or (5u) mod 128
+                  (u >= 128), value 16, or -16 when u mod 16 == 7
+      b1[u]     = 16 (u mod 3)   (same sign as the weight)
+      W2[v, :]  = 1 at column (3v + 1) mod 256, 1/2 at (7v + 2) mod 256, or
+                  -1 / -1/2 when v mod 32 == 5; b2[v] = +-16 with that sign
+      W3[o, :]  = 1 at column (5o + 3) mod 256, -1/4 at (11o + 7) mod 256;
+                  b3[o] = o / 64
+    W2 is not symmetric, so a transposed square layer changes the logits."""
+    W1 = np.zeros((256, 128))
+    b1 = np.zeros(256)
+    for u in range(256):
+        col = u % 128 if u < 128 else (5 * u) % 128
+        sgn = -1.0 if u % 16 == 7 else 1.0
+        W1[u, col] = 16.0 * sgn
+        b1[u] = 16.0 * (u % 3) * sgn
+    W2 = np.zeros((256, 256))
+    b2 = np.zeros(256)
+    for v in range(256):
+        sgn = -1.0 if v % 32 == 5 else 1.0
+        W2[v, (3 * v + 1) % 256] += 1.0 * sgn
+        W2[v, (7 * v + 2) % 256] += 0.5 * sgn
+        b2[v] = 16.0 * sgn
+    W3 = np.zeros((512, 256))
+    b3 = np.zeros(512)
+    for o in range(512):
+        W3[o, (5 * o + 3) % 256] += 1.0
+        W3[o, (11 * o + 7) % 256] += -0.25
+        b3[o] = o / 64.0
+    x = np.array([[1.0 + j / 128.0 for j in range(128)]])
+    return [W1, b1, W2, b2, W3, b3], x
+
+
+def _hand_logits():
+    """The same network evaluated entry by entry from its description, with
+    exact fractions and GELU taken as its two saturated branches."""
+    from fractions import Fraction as F
+    x = [F(1) + F(j, 128) for j in range(128)]
+
+    def act(z):
+        assert z == 0 or abs(z) >= 16
+        return z if z > 0 else F(0)
+
+    h1 = []
+    for u in range(256):
+        col = u % 128 if u < 128 else (5 * u) % 128
+        sgn = -1 if u % 16 == 7 else 1
+        h1.append(act(16 * sgn * x[col] + 16 * (u % 3) * sgn))
+    h2 = []
+    for v in range(256):
+        sgn = -1 if v % 32 == 5 else 1
+        a, b = (3 * v + 1) % 256, (7 * v + 2) % 256
+        z = sgn * (h1[a] + F(1, 2) * h1[b]) + 16 * sgn
+        h2.append(act(z))
+    out = []
+    for o in range(512):
+        a, b = (5 * o + 3) % 256, (11 * o + 7) % 256
+        out.append(h2[a] - F(1, 4) * h2[b] + F(o, 64))
+    return out
+
+
+def test_mlp_forward_dyadic_network_exact(orc):
+    """The forward composition (128 -> 256 -> 256 -> 512, GELU after the two
+    hidden layers, biases added before the activation, weights output-major)
+    equals a hand evaluation of an exactly representable network.  A
+    transposed W2, a missing bias or GELU on the output layer changes logits
+    by whole units."""
+    params, x = _dyadic_net()
+    logits, _ = orc.mlp_forward(params, x)
+    want = _hand_logits()
+    assert logits.shape == (1, 512)
+    for o in range(512):
+        assert logits[0, o] == float(want[o]), o
+    # the pin separates the two orientations of the square layer
+    alt = list(params)
+    alt[2] = params[2].T.copy()
+    bad, _ = orc.mlp_forward(alt, x)
+    assert np.abs(bad - logits).max() >= 1.0
