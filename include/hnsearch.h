@@ -74,6 +74,14 @@ enum { HN_PREC_FP32 = 0, HN_PREC_BF16 = 1, HN_PREC_FP8 = 2, HN_PREC_INT8 = 3 };
  *            without a seed. */
 enum { HN_SEED_PLAIN = 0, HN_SEED_LEARNED = 1, HN_SEED_WINDOW = 2 };
 
+/* Precision of the plain seed's argmax scan (Algorithm 1 step 1).  Any entry
+ * whose scan score is near-maximal is an admissible seed (its canonical sim
+ * is the bound), so the argmax scan may run on the bf16 copy whatever the
+ * filter's precision: BF16 (the default) contracts four times faster than
+ * FP32 on the matrix cores; FP32 runs the argmax on the float32 prefix, the
+ * all-float32 form of the search.  The result is the same either way. */
+enum { HN_SEED_SCAN_BF16 = 0, HN_SEED_SCAN_FP32 = 1 };
+
 /* The seed model: an MLP 128 -> 256 -> 256 -> 512 with exact GELU
  * (x Phi(x)) after the two hidden layers, bf16 weights, float32 biases,
  * float32 accumulation, one output per anchor entry.  Its parameters are one
@@ -82,24 +90,26 @@ enum { HN_SEED_PLAIN = 0, HN_SEED_LEARNED = 1, HN_SEED_WINDOW = 2 };
  * (output-major).  Forward passes round the weights to bf16 (nearest even). */
 enum { HN_MLP_IN = 128, HN_MLP_H = 256, HN_MLP_OUT = 512, HN_MLP_PARAMS = 230400 };
 
-/* Build flags. */
+/* Build flags (any other bit: HN_ERR_INVALID_ARG).  Every build makes the
+ * float32 prefix stream, the BF16 copy and, for k <= 32, the FP8 and INT8
+ * copies (4, 2, 1 and 1 bytes per prefix element) beside the float32 rows. */
 enum {
-    HN_BUILD_NO_VALIDATE = 1u << 0, /* skip the block-norm check (bounds stay
-                                       rigorous: they use measured norms) */
-    HN_BUILD_LOW_PRECISION = 1u << 1 /* accepted, no effect: the BF16 copy and
-                                        (k <= 32) the FP8 and INT8 copies are
-                                        always built, at 2, 1 and 1 bytes per
-                                        prefix element */
+    HN_BUILD_NO_VALIDATE = 1u << 0 /* skip the block-norm check (bounds stay
+                                      rigorous: they use measured norms) */
 };
 
 typedef struct {
     int32_t precision;    /* HN_PREC_*; FP32 by default */
     int32_t seed;         /* HN_SEED_*; plain by default */
     int32_t query_tiles;  /* MFMA query tiles per wave (16 or 32 queries each,
-                             by K and precision); 0 = tuned; values the build
-                             does not compile fall to the largest smaller one */
+                             by K and precision); 0 = a fixed heuristic of q,
+                             K and precision (the smallest query block that
+                             covers q, within the register budget); values the
+                             build does not compile fall to the largest
+                             smaller one */
     int32_t chunk_blocks; /* entry blocks (16 or 32 entries) per work item;
-                             0 = tuned */
+                             0 = a fixed heuristic (whole rounds of the
+                             persistent grid, about 8192 items) */
     int64_t survivor_cap; /* capacity of the survivor list in (query, entry)
                              pairs; 0 = automatic.  Queries whose survivors
                              do not fit are finished exactly by a second
@@ -108,6 +118,8 @@ typedef struct {
                              alpha: soft mode of Section 7, which replaces
                              alpha by beta in the skip test and is no longer
                              exact. */
+    int32_t seed_scan;    /* HN_SEED_SCAN_*: precision of the plain seed's
+                             argmax scan; BF16 (0) by default */
 } hn_search_opts;
 
 /* Optional per-query device outputs (any member may be NULL). */
@@ -341,7 +353,8 @@ typedef struct hn_multi_plan hn_multi_plan; /* opaque */
 /* Plan a search of q_counts[d] queries (host int64 [n_db], >= 0) against
  * ixs[d] (each k <= 32, all on the current device) with the given options
  * (precision, query_tiles, chunk_blocks, survivor_cap, beta; the seed must be
- * HN_SEED_PLAIN, else HN_ERR_UNSUPPORTED).  Synchronises.  The indexes must
+ * HN_SEED_PLAIN, else HN_ERR_UNSUPPORTED; a plan runs its argmax scan in its
+ * own precision and ignores seed_scan).  Synchronises.  The indexes must
  * outlive the plan. */
 int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db, const int64_t *q_counts,
                          const hn_search_opts *opts, hn_multi_plan **out);
@@ -359,6 +372,28 @@ int hn_multi_plan_info(const hn_multi_plan *plan, int64_t *total_queries, int64_
                        int32_t *scan_launches);
 
 void hn_multi_plan_free(hn_multi_plan *plan);
+
+/* ------------------------------------------------------------ device memory
+ * Not part of the paper: the library's own device allocations (index copies,
+ * seed models, per-stream scratch arenas, multi-database plans) counted
+ * against an optional budget, for processes that share a GPU and for tests of
+ * the out-of-memory paths.  Scratch arenas are kept per (device, stream) and
+ * grow on demand; two host threads must not enqueue on the same stream at
+ * once, since their calls would share one arena. */
+
+/* Cap the bytes the library holds at once in device allocations: a request
+ * that would exceed it fails with HN_ERR_OOM, as a full device does, and the
+ * failing call releases what it had taken.  max_bytes = 0 removes the cap
+ * (the default); max_bytes < 0 is HN_ERR_INVALID_ARG.  Holdings above a new
+ * cap are not released. */
+int hn_set_memory_budget(int64_t max_bytes);
+
+/* Bytes the library holds now in device allocations (all devices). */
+int64_t hn_memory_held(void);
+
+/* Release the scratch arenas kept for `stream` on the current device, after
+ * synchronising it.  Later calls on that stream allocate them again. */
+int hn_release_scratch(void *stream);
 
 /* Message for the calling thread's last non-OK status ("" if none). */
 const char *hn_last_error(void);

@@ -20,9 +20,9 @@ HN_ERR_UNSUPPORTED = -5
 
 HN_PREC_FP32, HN_PREC_BF16, HN_PREC_FP8, HN_PREC_INT8 = 0, 1, 2, 3
 HN_SEED_PLAIN, HN_SEED_LEARNED, HN_SEED_WINDOW = 0, 1, 2
+HN_SEED_SCAN_BF16, HN_SEED_SCAN_FP32 = 0, 1
 HN_MLP_IN, HN_MLP_H, HN_MLP_OUT, HN_MLP_PARAMS = 128, 256, 512, 230400
 HN_BUILD_NO_VALIDATE = 1 << 0
-HN_BUILD_LOW_PRECISION = 1 << 1
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -33,7 +33,8 @@ _dbl = ctypes.c_double
 
 class SearchOpts(ctypes.Structure):
     _fields_ = [("precision", _i32), ("seed", _i32), ("query_tiles", _i32),
-                ("chunk_blocks", _i32), ("survivor_cap", _i64), ("beta", _dbl)]
+                ("chunk_blocks", _i32), ("survivor_cap", _i64), ("beta", _dbl),
+                ("seed_scan", _i32)]
 
 
 class SearchAux(ctypes.Structure):
@@ -88,6 +89,9 @@ SIGNATURES = {
     "hn_multi_plan_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                                   ctypes.POINTER(_i32)]),
     "hn_multi_plan_free": (None, [_vp]),
+    "hn_set_memory_budget": (_i32, [_i64]),
+    "hn_memory_held": (_i64, []),
+    "hn_release_scratch": (_i32, [_vp]),
     "hn_last_error": (ctypes.c_char_p, []),
 }
 

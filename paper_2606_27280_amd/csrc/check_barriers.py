@@ -28,7 +28,11 @@ def annotation(body, i):
 
 
 def check(asm, verbose=False):
-    starts = [i for i, l in enumerate(asm) if re.match(r'^_Z\S+:', l)]
+    # data symbols (device globals) are labels too, with no function end
+    objects = {m.group(1) for l in asm for m in [re.match(r'^\s*\.type\s+(\S+),\s*@object', l)]
+               if m}
+    starts = [i for i, l in enumerate(asm)
+              if re.match(r'^_Z\S+:', l) and l.split(':')[0] not in objects]
     flagged = []
     for si in starts:
         sym = asm[si].split(':')[0]

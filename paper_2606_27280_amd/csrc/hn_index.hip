@@ -24,6 +24,47 @@ int fail(int code, const char *fmt, ...) {
 }
 void clear_error() { g_err[0] = 0; }
 
+// ------------------------------------------------------- device memory
+
+namespace {
+std::mutex g_mem_mu;
+std::unordered_map<void *, size_t> g_mem_size;
+int64_t g_mem_held = 0;
+int64_t g_mem_budget = 0;  // 0: no budget
+}  // namespace
+
+hipError_t dev_malloc(void **p, size_t bytes) {
+    *p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_mem_mu);
+        if (g_mem_budget > 0 && g_mem_held + (int64_t)bytes > g_mem_budget)
+            return hipErrorOutOfMemory;
+        g_mem_held += (int64_t)bytes;  // reserved before the call
+    }
+    const hipError_t e = hipMalloc(p, bytes);
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    if (e != hipSuccess) {
+        g_mem_held -= (int64_t)bytes;
+        *p = nullptr;
+        return e;
+    }
+    g_mem_size[*p] = bytes;
+    return hipSuccess;
+}
+
+void dev_free(void *p) {
+    if (!p) return;
+    {
+        std::lock_guard<std::mutex> lk(g_mem_mu);
+        auto it = g_mem_size.find(p);
+        if (it != g_mem_size.end()) {
+            g_mem_held -= (int64_t)it->second;
+            g_mem_size.erase(it);
+        }
+    }
+    (void)hipFree(p);
+}
+
 // ---------------------------------------------------------------- arenas
 
 namespace {
@@ -55,12 +96,12 @@ int arena_for(void *stream, size_t bytes, Arena **out, int slot) {
         if (a->base) {
             // the old buffer may still be in use by work queued on the stream
             HN_HIP(hipStreamSynchronize((hipStream_t)stream));
-            HN_HIP(hipFree(a->base));
+            dev_free(a->base);
             a->base = nullptr;
             a->cap = 0;
         }
         size_t want = bytes + bytes / 4 + (1u << 20);
-        if (hipMalloc(&a->base, want) != hipSuccess) {
+        if (dev_alloc(&a->base, want) != hipSuccess) {
             (void)hipGetLastError();
             return fail(HN_ERR_OOM, "scratch allocation of %zu bytes failed", want);
         }
@@ -68,6 +109,27 @@ int arena_for(void *stream, size_t bytes, Arena **out, int slot) {
     }
     a->used = 0;
     *out = a;
+    return HN_OK;
+}
+
+int release_arenas(void *stream) {
+    int dev = 0;
+    HN_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_arena_mu);
+    bool synced = false;
+    for (auto it = g_arenas.begin(); it != g_arenas.end();) {
+        if (it->first.device == dev && it->first.stream == stream) {
+            if (!synced) {
+                HN_HIP(hipStreamSynchronize((hipStream_t)stream));
+                synced = true;
+            }
+            dev_free(it->second->base);
+            delete it->second;
+            it = g_arenas.erase(it);
+        } else {
+            ++it;
+        }
+    }
     return HN_OK;
 }
 
@@ -272,14 +334,14 @@ double round_up_norm(double v) { return v * (1.0 + ldexp(1.0, -40)); }
 
 void free_index(hn_index *ix) {
     if (!ix) return;
-    if (ix->rows) (void)hipFree(ix->rows);
-    if (ix->major32) (void)hipFree(ix->major32);
-    if (ix->major16) (void)hipFree(ix->major16);
-    if (ix->major8) (void)hipFree(ix->major8);
-    if (ix->major_i8) (void)hipFree(ix->major_i8);
-    if (ix->seed_w) (void)hipFree(ix->seed_w);
-    if (ix->seed_b) (void)hipFree(ix->seed_b);
-    if (ix->seed_anchor) (void)hipFree(ix->seed_anchor);
+    dev_free(ix->rows);
+    dev_free(ix->major32);
+    dev_free(ix->major16);
+    dev_free(ix->major8);
+    dev_free(ix->major_i8);
+    dev_free(ix->seed_w);
+    dev_free(ix->seed_b);
+    dev_free(ix->seed_anchor);
     delete ix;
 }
 
@@ -289,6 +351,24 @@ void free_index(hn_index *ix) {
 using namespace hn;
 
 extern "C" const char *hn_last_error(void) { return hn::g_err; }
+
+extern "C" int hn_set_memory_budget(int64_t max_bytes) {
+    clear_error();
+    if (max_bytes < 0) return fail(HN_ERR_INVALID_ARG, "max_bytes must be >= 0");
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    g_mem_budget = max_bytes;
+    return HN_OK;
+}
+
+extern "C" int64_t hn_memory_held(void) {
+    std::lock_guard<std::mutex> lk(g_mem_mu);
+    return g_mem_held;
+}
+
+extern "C" int hn_release_scratch(void *stream) {
+    clear_error();
+    return release_arenas(stream);
+}
 
 extern "C" void hn_free_index(hn_index *ix) {
     if (!ix) return;
@@ -329,6 +409,8 @@ extern "C" int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, 
     if (!(alpha >= 0.0 && alpha < 1.0)) return fail(HN_ERR_INVALID_ARG, "alpha must be in [0,1)");
     if (n < 1) return fail(HN_ERR_INVALID_ARG, "n must be >= 1");
     if (n >= (int64_t)1 << 31) return fail(HN_ERR_UNSUPPORTED, "n must be < 2^31");
+    if (flags & ~(uint32_t)HN_BUILD_NO_VALIDATE)
+        return fail(HN_ERR_INVALID_ARG, "unknown build flags 0x%x", flags);
     hipStream_t s = (hipStream_t)stream;
 
     hn_index *ix = new (std::nothrow) hn_index();
@@ -344,16 +426,16 @@ extern "C" int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, 
 
     BuildStats *st = nullptr;
     auto cleanup = [&](int code) {
-        if (st) (void)hipFree(st);
+        dev_free(st);
         free_index(ix);
         return code;
     };
-    if (hipMalloc(&st, sizeof(BuildStats)) != hipSuccess ||
-        hipMalloc(&ix->rows, (size_t)n * kDim * sizeof(float)) != hipSuccess ||
-        hipMalloc(&ix->major32, (size_t)ix->n_pad * ix->kp * sizeof(float)) != hipSuccess ||
-        hipMalloc(&ix->major16, (size_t)ix->n_pad * ix->kb * sizeof(uint16_t)) != hipSuccess ||
-        (ix->k8 && hipMalloc(&ix->major8, (size_t)ix->n_pad * ix->k8) != hipSuccess) ||
-        (ix->k8 && hipMalloc(&ix->major_i8, (size_t)ix->n_pad * ix->k8) != hipSuccess)) {
+    if (dev_alloc(&st, sizeof(BuildStats)) != hipSuccess ||
+        dev_alloc(&ix->rows, (size_t)n * kDim * sizeof(float)) != hipSuccess ||
+        dev_alloc(&ix->major32, (size_t)ix->n_pad * ix->kp * sizeof(float)) != hipSuccess ||
+        dev_alloc(&ix->major16, (size_t)ix->n_pad * ix->kb * sizeof(uint16_t)) != hipSuccess ||
+        (ix->k8 && dev_alloc(&ix->major8, (size_t)ix->n_pad * ix->k8) != hipSuccess) ||
+        (ix->k8 && dev_alloc(&ix->major_i8, (size_t)ix->n_pad * ix->k8) != hipSuccess)) {
         (void)hipGetLastError();
         fail(HN_ERR_OOM, "device allocation failed for n=%lld", (long long)n);
         return cleanup(HN_ERR_OOM);
@@ -403,7 +485,7 @@ extern "C" int hn_build_index(const float *db, int64_t n, int32_t d, int32_t k, 
     ix->res8 = round_up_norm(key_to_double_host(h.key_res8));
     ix->mu_major_i8 = round_up_norm(key_to_double_host(h.key_majori));
     ix->res_i8 = round_up_norm(key_to_double_host(h.key_resi));
-    (void)hipFree(st);
+    dev_free(st);
     *out = ix;
     return HN_OK;
 }

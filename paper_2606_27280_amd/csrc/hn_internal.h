@@ -37,6 +37,16 @@ inline int f32_width(int k) {
 // Round K up to the bf16 stream width (one 16x16x16 or 16x16x32 step per 16/32).
 inline int bf16_width(int k) { return k <= 16 ? 16 : (k <= 32 ? 32 : (k <= 64 ? 64 : 128)); }
 
+// Device allocations of the library, counted against the memory budget
+// (hn_set_memory_budget).  dev_malloc fails with hipErrorOutOfMemory when
+// the budget would be exceeded; dev_free(nullptr) does nothing.
+hipError_t dev_malloc(void **p, size_t bytes);
+void dev_free(void *p);
+template <class T>
+inline hipError_t dev_alloc(T **p, size_t bytes) {
+    return dev_malloc(reinterpret_cast<void **>(p), bytes);
+}
+
 // Per-stream scratch arena: grows on demand, reused by later calls on the
 // same stream (stream order makes reuse safe).
 struct Arena {

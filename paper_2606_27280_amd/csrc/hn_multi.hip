@@ -104,7 +104,7 @@ void plan_destroy(hn_multi_plan *P) {
     if (!P) return;
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
-    if (P->mem) (void)hipFree(P->mem);
+    dev_free(P->mem);
     delete P;
 }
 
@@ -340,7 +340,7 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
                  o_sa = add(n_db, sizeof(ScanArgs)), o_sf = add(n_db, sizeof(ScanArgs)),
                  o_seed = add(n_db, sizeof(SeedArgs)), o_prep = add(n_db, sizeof(PrepArgs)),
                  o_db = add(n_db, sizeof(DbRef));
-    if (hipMalloc(&P->mem, bytes) != hipSuccess) {
+    if (dev_alloc(&P->mem, bytes) != hipSuccess) {
         (void)hipGetLastError();
         plan_destroy(P);
         return fail(HN_ERR_OOM, "plan allocation of %zu bytes failed", bytes);

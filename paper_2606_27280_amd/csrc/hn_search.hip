@@ -17,8 +17,10 @@ struct Work {
     int cfg = 0;
     int precision = HN_PREC_FP32;
     int width = 0;
-    Plan seed_plan;  // the argmax (seed) scan: bf16 stream
+    Plan seed_plan;  // the argmax (seed) scan
     int seed_cfg = 0;
+    int seed_precision = HN_PREC_BF16;  // HN_PREC_BF16 or HN_PREC_FP32
+    int seed_width = 0;
     int shape = 16;  // tile shape of the argmax scan (16 or 32): decodes its groups
     const void *stream_x = nullptr;
     float *op32 = nullptr;
@@ -87,16 +89,18 @@ int validate_opts(const hn_index *ix, const hn_search_opts *o) {
     if (o->survivor_cap < 0) return fail(HN_ERR_INVALID_ARG, "survivor_cap must be >= 0");
     if (!(o->beta < 0.0 || (o->beta >= 0.0 && o->beta <= ix->alpha)))
         return fail(HN_ERR_INVALID_ARG, "beta must be < 0 (exact) or in [0, alpha]");
+    if (o->seed_scan != HN_SEED_SCAN_BF16 && o->seed_scan != HN_SEED_SCAN_FP32)
+        return fail(HN_ERR_INVALID_ARG, "seed_scan must be HN_SEED_SCAN_BF16 or HN_SEED_SCAN_FP32");
     return HN_OK;
 }
 
-// Prepare queries, run the plain-seed pass and compute thresholds.  With
-// `lower` the seed pass is skipped and L (and its entry, lower_idx, if not
-// NULL) is taken from the caller.  `window`: also the single-pass window
-// (W.win, W.win_scan, W.init_best) and the pair values.
-int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_search_opts &o,
-               const double *lower, const int64_t *lower_idx, int64_t cap, Work &W,
-               hipStream_t s, bool window = false, int topk = 0) {
+// Launch shapes of a search: the filter (or window) scan and the argmax
+// (seed) scan.  The seed scan runs on the bf16 copy unless opts.seed_scan
+// asks for float32: the seed only has to be a real entry with a near-maximal
+// score (its float64 sim is the bound), and bf16 contracts four times faster
+// than float32 on the matrix cores.
+int plan_stage(const hn_index *ix, int64_t q, const hn_search_opts &o, Work &W, bool window,
+               int topk) {
     W.precision = o.precision;
     W.width = stream_width(ix, W.precision);
     W.stream_x = stream_of(ix, W.precision);
@@ -112,12 +116,9 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     const int64_t one_qb = (int64_t)kCfgNQ[W.cfg] * kCfgWQ[W.cfg] * ti.cols;
     W.plan = make_plan(ix->n, q, W.cfg, o.chunk_blocks, ti.rows, ti.cols,
                        q <= one_qb && fslots >= kXcds ? 2 * fslots : 8192, fslots);
-    const Plan &p = W.plan;
-    // The argmax (seed) scan runs on the bf16 copy whatever the filter's
-    // precision: the seed only has to be a real entry with a near-maximal
-    // score (its float64 sim is the bound), and bf16 contracts four times
-    // faster than float32 on the matrix cores.
-    const TileInfo tis = tile_info(HN_PREC_BF16, ix->kb);
+    W.seed_precision = o.seed_scan == HN_SEED_SCAN_FP32 ? HN_PREC_FP32 : HN_PREC_BF16;
+    W.seed_width = stream_width(ix, W.seed_precision);
+    const TileInfo tis = tile_info(W.seed_precision, W.seed_width);
     W.seed_cfg = pick_cfg(q, tis.cols, tis.cost, o.query_tiles);
     if (W.seed_cfg < 0)
         return fail(HN_ERR_INVALID_ARG, "query_tiles=%d is not available for this width",
@@ -126,17 +127,21 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     // One query block: two rounds of the grid as for the filter plan, which
     // also shortens the seed kernel's walk over the per-chunk partials (one
     // per chunk and query).
-    const int64_t sslots = scan_slots(HN_PREC_BF16, kArgmax, ix->kb, W.seed_cfg);
+    const int64_t sslots = scan_slots(W.seed_precision, kArgmax, W.seed_width, W.seed_cfg);
     const int64_t one_sqb = (int64_t)kCfgNQ[W.seed_cfg] * kCfgWQ[W.seed_cfg] * tis.cols;
     W.seed_plan = make_plan(ix->n, q, W.seed_cfg, o.chunk_blocks, tis.rows, tis.cols,
                             q <= one_sqb && sslots >= kXcds ? 2 * sslots : 8192, sslots,
                             topk > 1 ? 2 * (int64_t)topk : 1);
     W.shape = tis.rows;
-    const Plan &sp = W.seed_plan;
+    return HN_OK;
+}
+
+// Scratch bytes of one search besides its pair list, and per pair.
+size_t stage_bytes(const hn_index *ix, int64_t q, const Work &W, bool window,
+                   size_t *per_pair) {
+    const Plan &p = W.plan, &sp = W.seed_plan;
     const int64_t qp = std::max(p.q_pad, sp.q_pad);
     const size_t part = std::max((size_t)p.n_chunks * p.q_pad, (size_t)sp.n_chunks * sp.q_pad);
-    W.cap = cap;
-
     size_t bytes = 0;
     auto add = [&](size_t count, size_t sz) { bytes += (count * sz + 255) & ~size_t(255); };
     add(qp * ix->kp, 4);
@@ -157,23 +162,42 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     add(4, 8);
     add(kWorkWords, 4);
     add(p.n_items, 4);
-    add(cap, sizeof(int2));
-    add(cap, 8);
     if (window) {
         add(qp, 8);
         add(qp, 4);
         add(qp, 4);
         add(q, 4);
-        add(cap, 4);
         add(q, 8);
         add(q, 8);
     }
+    // pairs (int2), their float64 sims and, with the window, their scores;
+    // plus the rounding of each of those arrays to 256 bytes
+    *per_pair = sizeof(int2) + 8 + (window ? 4 : 0);
+    return bytes + 3 * 256;
+}
+
+// Prepare queries, run the plain-seed pass and compute thresholds.  With
+// `lower` the seed pass is skipped and L (and its entry, lower_idx, if not
+// NULL) is taken from the caller.  `window`: also the single-pass window
+// (W.win, W.win_scan, W.init_best) and the pair values.
+int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_search_opts &o,
+               const double *lower, const int64_t *lower_idx, int64_t cap, Work &W,
+               hipStream_t s, bool window = false, int topk = 0) {
+    int rc = plan_stage(ix, q, o, W, window, topk);
+    if (rc) return rc;
+    const Plan &sp = W.seed_plan;
+    const int64_t qp = std::max(W.plan.q_pad, sp.q_pad);
+    const size_t part =
+        std::max((size_t)W.plan.n_chunks * W.plan.q_pad, (size_t)sp.n_chunks * sp.q_pad);
+    W.cap = cap;
+    size_t per_pair = 0;
+    const size_t bytes = stage_bytes(ix, q, W, window, &per_pair) + (size_t)cap * per_pair;
     Arena *ar = nullptr;
-    int rc = arena_for((void *)s, bytes, &ar);
+    rc = arena_for((void *)s, bytes, &ar);
     if (rc) return rc;
     W.op32 = ar->take<float>(qp * ix->kp);
     W.op16 = ar->take<uint16_t>(qp * ix->kb);
-    W.op32 = W.precision == HN_PREC_FP32 ? W.op32 : nullptr;
+    if (W.precision != HN_PREC_FP32 && W.seed_precision != HN_PREC_FP32) W.op32 = nullptr;
     W.op8 = W.precision == HN_PREC_FP8 ? ar->take<uint8_t>(qp * ix->k8) : nullptr;
     W.opi = W.precision == HN_PREC_INT8 ? ar->take<int8_t>(qp * ix->k8) : nullptr;
     W.qn = ar->take<QNorm>(qp);
@@ -191,18 +215,18 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     W.counter = ar->take<unsigned long long>(4);
     W.n_flagged = W.counter + 1;
     W.work = ar->take<unsigned>(kWorkWords);
-    W.redo = ar->take<int>(p.n_items);
-    W.pairs = ar->take<int2>(cap);
-    W.psim = ar->take<double>(cap);
+    W.redo = ar->take<int>(W.plan.n_items);
     if (window) {
         W.win = ar->take<double>(qp);
         W.win_scan = ar->take<float>(qp);
         W.init_best = ar->take<float>(qp);
         W.thr_ref = ar->take<float>(q);
-        W.pair_val = ar->take<float>(cap);
         W.lower = ar->take<double>(q);
         W.lower_idx = ar->take<int64_t>(q);
     }
+    W.pairs = ar->take<int2>(cap);
+    W.psim = ar->take<double>(cap);
+    if (window) W.pair_val = ar->take<float>(cap);
 
     launch_prep(ix, queries, q, qp, W, s);
     HN_HIP(hipGetLastError());
@@ -221,10 +245,11 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     if (!lower) {
         ScanArgs A;
         memset(&A, 0, sizeof A);
-        A.x = ix->major16;
-        A.x_stride = ix->kb;
-        A.qs = W.op16;
-        A.q_stride = ix->kb;
+        const bool f32 = W.seed_precision == HN_PREC_FP32;
+        A.x = f32 ? (const void *)ix->major32 : (const void *)ix->major16;
+        A.x_stride = W.seed_width;
+        A.qs = f32 ? (const void *)W.op32 : (const void *)W.op16;
+        A.q_stride = W.seed_width;
         A.n = ix->n;
         A.n_blocks = sp.n_blocks;
         A.chunk_blocks = sp.chunk_blocks;
@@ -237,7 +262,7 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
         A.part_idx = W.part_idx;
         A.redo = W.redo;
         A.redo_count = W.work + 2 * kXcds;
-        rc = launch_scan<kArgmax>(HN_PREC_BF16, ix->kb, W.seed_cfg, sp, A, s);
+        rc = launch_scan<kArgmax>(W.seed_precision, W.seed_width, W.seed_cfg, sp, A, s);
         if (rc) return rc;
     }
 

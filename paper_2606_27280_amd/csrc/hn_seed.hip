@@ -771,10 +771,17 @@ extern "C" int hn_set_seed_model(hn_index *ix, const float *params, const int64_
     HN_HIP(hipMemcpy(h.data(), anchors, sizeof(int64_t) * n_anchor, hipMemcpyDeviceToHost));
     std::vector<int32_t> h32(h.begin(), h.end());
     if (!ix->seed_w) {
-        if (hipMalloc(&ix->seed_w, kWeights * sizeof(uint16_t)) != hipSuccess ||
-            hipMalloc(&ix->seed_b, kBiases * sizeof(float)) != hipSuccess ||
-            hipMalloc(&ix->seed_anchor, kOut * sizeof(int32_t)) != hipSuccess) {
+        if (dev_alloc(&ix->seed_w, kWeights * sizeof(uint16_t)) != hipSuccess ||
+            dev_alloc(&ix->seed_b, kBiases * sizeof(float)) != hipSuccess ||
+            dev_alloc(&ix->seed_anchor, kOut * sizeof(int32_t)) != hipSuccess) {
             (void)hipGetLastError();
+            // all or nothing: a later call allocates the three again
+            dev_free(ix->seed_w);
+            dev_free(ix->seed_b);
+            dev_free(ix->seed_anchor);
+            ix->seed_w = nullptr;
+            ix->seed_b = nullptr;
+            ix->seed_anchor = nullptr;
             return fail(HN_ERR_OOM, "seed model allocation failed");
         }
     }

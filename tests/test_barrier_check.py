@@ -79,3 +79,12 @@ def test_flags_divergent_inner_loop_and_its_parent_barrier():
 def test_uniform_loop_with_barrier_passes():
     n, flagged = cb.check(CLEAN)
     assert n == 1 and flagged == []
+
+
+def test_device_globals_are_not_kernels():
+    """A device global's label (no function end) is skipped, not parsed as a
+    kernel."""
+    asm = DIVERGENT_INNER + ["\t.type\t_ZN2hn7scratchE,@object", "_ZN2hn7scratchE:",
+                             "\t.zero\t64"]
+    total, flagged = cb.check(asm)
+    assert len(flagged) >= 1

@@ -46,6 +46,27 @@ def assert_exact(gi, gs, ri, rs, what=""):
     assert (d <= SIM_TOL).all(), "%s: max |dsim| = %g" % (what, d.max())
 
 
+def exact_must(db, q, L):
+    """{i : sim(q, x_i) >= L} with the canonical float64 sim: the entries an
+    exact search must rescore (the bound of Eq. 3 is only a means to this).
+    A float64 matmul screens; entries within 1e-9 of L are decided by the
+    oracle's canonical sim."""
+    s = db.astype(np.float64) @ q.astype(np.float64)
+    near = np.nonzero(s >= L - 1e-9)[0]
+    return {int(i) for i in near if oracle.sim(q, db[i]) >= L}
+
+
+def self_queries(db, k, alpha, count):
+    """Rows of the database as queries (q = x_i), the rows whose stored minor
+    block exceeds sqrt(alpha) in norm (float32 rounding) first: for them the
+    literal Eq. 3 bound fails on the self pair."""
+    x = db.astype(np.float64)
+    over = np.nonzero((x[:, k:] ** 2).sum(1) > alpha)[0]
+    rest = np.setdiff1d(np.arange(len(db)), over)
+    pick = np.concatenate([over[: count // 2], rest[: count - min(len(over), count // 2)]])
+    return db[pick[:count]].copy(), int(min(len(over), count // 2))
+
+
 # ------------------------------------------------------------ scan numerics
 
 @pytest.mark.parametrize("k", [1, 5, 8, 16, 40, 127])
@@ -218,6 +239,9 @@ def test_edge_shapes_exact(hn, n, k, alpha, nq):
     if n >= 8:  # exact ties: duplicated rows
         db[n - 1] = db[0]
         db[n // 2] = db[3]
+    # exact self-queries (q = x_i), rows with a float32 minor-norm excess first
+    sq, _ = self_queries(db, k, alpha, min(n, 8))
+    qs = np.concatenate([qs, sq])
     for prec in ("fp32", "bf16", "fp8", "int8"):
         if prec in ("fp8", "int8") and k > 32:
             continue  # no fp8 / int8 copy above k = 32 (checked in test_invalid_inputs)
@@ -316,7 +340,7 @@ def test_invalid_inputs(hn):
         ix.search(dev(hn_inputs.make_queries(db40, 40, alpha, 4, 1, 9)), precision="fp8")
     assert e.value.code == -5
     ix.close()
-    with pytest.raises(hn.HNError):
+    with pytest.raises(ValueError):  # the binding checks the width
         hn.Index(dev(db[:, :64]), k, alpha)
 
 
@@ -364,12 +388,15 @@ def test_filter_survivor_sets_match_oracle(hn):
     pairs = pairs.cpu().numpy()
     L = L.cpu().numpy()
     slack = slack.cpu().numpy()
+    need = [exact_must(db, qs[qi], L[qi]) for qi in range(len(qs))]
     for qi in range(len(qs)):
         got = set(pairs[pairs[:, 0] == qi, 1].tolist())
         must = set(oracle.survivor_list(db, qs[qi], w.k, w.alpha, L[qi] + 2.0 ** -40).tolist())
         may = set(oracle.survivor_list(db, qs[qi], w.k, w.alpha,
                                        L[qi] - 2 * slack[qi] - 2.0 ** -20).tolist())
         assert must <= got <= may, qi
+        # what exactness needs: every entry whose full sim reaches L
+        assert need[qi] <= got, qi
     # the low-precision filters against the same sets, within their own slack
     for prec in ("bf16", "fp8", "int8"):
         say("filter survivors: %s" % prec)
@@ -381,6 +408,7 @@ def test_filter_survivor_sets_match_oracle(hn):
             may = set(oracle.survivor_list(db, qs[qi], w.k, w.alpha,
                                            L[qi] - 2 * ps[qi] - 2.0 ** -20).tolist())
             assert must <= got <= may, (prec, qi)
+            assert need[qi] <= got, (prec, qi)
     # a lower bound of -inf keeps everything; +inf keeps nothing
     lo = torch.full((3,), -math.inf, dtype=torch.float64, device="cuda:0")
     _, c_all, _ = ix.filter_survivors(dev(qs[:3]), lo, cap=0)
@@ -423,6 +451,67 @@ def test_int8_filter_equals_thresholded_scores(hn):
         assert got == want, qi
         n_checked += len(want)
     assert n_checked > 0
+    ix.close()
+
+
+@pytest.mark.parametrize("scale", [1.0, 2.0, 3.0])
+def test_minor_heavy_and_self_queries_need_the_norm_slack(hn, scale):
+    """Queries need not be HN-normalised.  With the minor block of q scaled up
+    (||q_m|| = scale sqrt(alpha)) the bound dot_K + alpha of Eq. 3 no longer
+    holds (the minor product reaches scale * alpha), and the search stays
+    exact only through the slack's norm term max(0, ||q_m|| mu_m - alpha).
+    Self-queries add the float32 case of the same term (rows whose stored
+    minor norm exceeds sqrt(alpha)).  Every precision must return the
+    oracle's result, and every entry whose full sim reaches the GPU's L must
+    survive the filter."""
+    k, alpha = 16, 1 / 8
+    db = hn_inputs.make_db(6000, k, alpha, 20, 5600)
+    qs = hn_inputs.make_queries(db, k, alpha, 40, 8, 5601).astype(np.float64)
+    qs[:, k:] *= scale
+    qs = qs.astype(np.float32)
+    sq, n_over = self_queries(db, k, alpha, 16)
+    assert n_over > 0
+    qs = np.concatenate([qs, sq])
+    say("minor-heavy queries: scale=%g, %d self-queries (%d with norm excess)" % (
+        scale, len(sq), n_over))
+    ix = hn.Index(dev(db), k, alpha)
+    ref = oracle.bnb_top1(db, qs, k, alpha)
+    for prec in ("fp32", "bf16", "fp8", "int8"):
+        idx, sim, aux = ix.search(dev(qs), precision=prec, aux=True)
+        assert_exact(idx.cpu().numpy(), sim.cpu().numpy(), ref["idx"], ref["sim"],
+                     "minor x%g %s" % (scale, prec))
+        L = aux["seed_sim"]
+        pairs, cnt, _ = ix.filter_survivors(dev(qs), L, cap=1 << 22, precision=prec)
+        assert cnt == pairs.shape[0]
+        pairs = pairs.cpu().numpy()
+        Lh = L.cpu().numpy()
+        for qi in range(0, len(qs), 3):
+            got = set(pairs[pairs[:, 0] == qi, 1].tolist())
+            assert exact_must(db, qs[qi], Lh[qi]) <= got, (prec, qi)
+    ix.close()
+
+
+def test_seed_scan_precision_does_not_change_results(hn):
+    """The plain seed's argmax scan on the float32 prefix (the all-float32
+    search) and on the bf16 copy give the same exact results in every filter
+    precision; only the seed and the survivor counts may differ."""
+    w = hn_inputs.workload(1)
+    db = w.db()
+    qs = w.queries(db)
+    ix = hn.Index(dev(db), w.k, w.alpha)
+    ref = oracle.bnb_top1(db, qs, w.k, w.alpha)
+    for prec in ("fp32", "bf16", "fp8", "int8"):
+        for ss in ("fp32", "bf16"):
+            say("seed scan %s, filter %s" % (ss, prec))
+            idx, sim, aux = ix.search(dev(qs), precision=prec, seed_scan=ss, aux=True)
+            assert_exact(idx.cpu().numpy(), sim.cpu().numpy(), ref["idx"], ref["sim"],
+                         "seed_scan=%s %s" % (ss, prec))
+            si = aux["seed_idx"].cpu().numpy()
+            sv = aux["seed_sim"].cpu().numpy()
+            for qi in range(0, len(qs), 31):
+                assert sv[qi] == oracle.sim(qs[qi], db[si[qi]])
+    with pytest.raises(hn.HNError):
+        ix.search(dev(qs), seed_scan=5)
     ix.close()
 
 

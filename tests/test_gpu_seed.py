@@ -207,7 +207,7 @@ def test_seed_labels_match_oracle(hn):
     bad = dev(np.array([0, 4000], dtype=np.int64))
     with pytest.raises(hn.HNError):
         ix.seed_labels(bad, dev(qs[:2]))
-    with pytest.raises(hn.HNError):
+    with pytest.raises(ValueError):
         ix.set_seed_model(dev(hn_inputs.mlp_init(1)), dev(anchors))  # 64 != 512 anchors
     with pytest.raises(hn.HNError):
         ix.search(dev(qs[:3]), seed="learned")  # no model installed

@@ -106,8 +106,19 @@ def test_topk_small_list_second_pass_and_errors(hn):
     q2[3, 0] = np.nan
     idx, sim = ix.search_topk(dev(q2), 4)
     assert (idx.cpu().numpy()[3] == -1).all() and np.isnan(sim.cpu().numpy()[3]).all()
-    with pytest.raises(hn.HNError):
+    with pytest.raises(ValueError):
         ix.search_topk(dev(qs), 0)
-    with pytest.raises(hn.HNError):
+    with pytest.raises(ValueError):
         ix.search_topk(dev(qs), 129)
+    # the library's own check, through the C ABI
+    import ctypes
+    import torch
+    out_i = torch.empty((len(qs), 129), dtype=torch.int64, device="cuda:0")
+    out_s = torch.empty((len(qs), 129), dtype=torch.float64, device="cuda:0")
+    dq = dev(qs)
+    for bad in (0, 129):
+        rc = hn._lib.lib().hn_search_topk(ix._h, ctypes.c_void_p(dq.data_ptr()), len(qs), bad,
+                                          ctypes.c_void_p(out_i.data_ptr()),
+                                          ctypes.c_void_p(out_s.data_ptr()), None, None)
+        assert rc == hn._lib.HN_ERR_INVALID_ARG
     ix.close()
