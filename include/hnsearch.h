@@ -186,6 +186,33 @@ int hn_search_top1(const hn_index *ix, const float *queries, int64_t q, int64_t 
                    hn_search_stats *stats, void *stream);
 
 /*
+ * The search of hn_search_top1 for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same results, with every scratch buffer
+ * carved from one statically allocated device array of
+ * HN_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the library runs on holds
+ * until the process ends.  The call allocates and frees nothing and never
+ * synchronises.
+ *   opts   the plain seed with precision FP32 or BF16 (others:
+ *          HN_ERR_UNSUPPORTED); survivor_cap 0 sizes the pair list to what the
+ *          array leaves after the per-query buffers (queries whose survivors
+ *          do not fit are finished exactly by the exhaustive float64 pass);
+ *          a survivor_cap beyond that is HN_ERR_INVALID_ARG.
+ *   aux    as for hn_search_top1; there are no stats.
+ * The per-query buffers grow with q and with n / 16 (argmax partials): a call
+ * whose buffers besides a minimal pair list of 65,536 pairs exceed the array
+ * returns HN_ERR_INVALID_ARG and enqueues nothing; split the queries.  At
+ * n = 2^20 and K = 16, q = 10,000 fits.  The index's device must be current.
+ * Every call on one GPU uses the same array: calls that overlap in time on one
+ * GPU (on different streams, or from several threads) race and give wrong
+ * results; serialise them.
+ */
+#define HN_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int hn_search_top1_noalloc(const hn_index *ix, const float *queries, int64_t q,
+                           int64_t *out_idx, double *out_sim, const hn_search_opts *opts,
+                           const hn_search_aux *aux, void *stream);
+
+/*
  * Exact top-k (k = topk) per query: the topk entries of largest canonical
  * sim, ordered by (sim desc, index asc) — Algorithm 1 with the running best
  * replaced by the topk-th best.  The seed bound L is the topk-th best sim

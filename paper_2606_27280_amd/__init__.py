@@ -170,6 +170,22 @@ class Index:
             res.append({"survivors": st.survivors, "overflow_queries": st.overflow_queries})
         return tuple(res)
 
+    def search_noalloc(self, queries, precision="fp32", query_tiles=0, chunk_blocks=0,
+                       survivor_cap=0, beta=None, aux=False, stream=None, out=None,
+                       seed_scan="bf16"):
+        """hn_search_top1_noalloc: the same search with the library's static
+        per-GPU scratch (no device allocation inside the call; pass `out` to
+        allocate nothing at all).  Calls that overlap on one GPU race."""
+        qp = _rows(queries, "queries", self.device)
+        q = queries.shape[0]
+        idx, sim = _outputs(out, q, self.device)
+        o = _opts(precision, query_tiles, chunk_blocks, survivor_cap, beta, "plain", seed_scan)
+        auxd, a = self._aux(q) if aux else (None, None)
+        _lib.check(_lib.lib().hn_search_top1_noalloc(
+            self._h, qp, q, _ptr(idx), _ptr(sim), ctypes.byref(o),
+            ctypes.byref(a) if a is not None else None, _stream(stream)))
+        return (idx, sim, auxd) if aux else (idx, sim)
+
     def search_topk(self, queries, topk, precision="fp32", query_tiles=0, chunk_blocks=0,
                     survivor_cap=0, beta=None, stream=None, seed_scan="bf16"):
         """Exact top-k per query (hn_search_topk): (idx int64 [q][topk],

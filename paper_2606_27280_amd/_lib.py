@@ -23,6 +23,7 @@ HN_SEED_PLAIN, HN_SEED_LEARNED, HN_SEED_WINDOW = 0, 1, 2
 HN_SEED_SCAN_BF16, HN_SEED_SCAN_FP32 = 0, 1
 HN_MLP_IN, HN_MLP_H, HN_MLP_OUT, HN_MLP_PARAMS = 128, 256, 512, 230400
 HN_BUILD_NO_VALIDATE = 1 << 0
+HN_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -65,6 +66,8 @@ SIGNATURES = {
                              ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
     "hn_search_top1": (_i32, [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(SearchOpts),
                               ctypes.POINTER(SearchAux), ctypes.POINTER(SearchStats), _vp]),
+    "hn_search_top1_noalloc": (_i32, [_vp, _vp, _i64, _vp, _vp, ctypes.POINTER(SearchOpts),
+                                      ctypes.POINTER(SearchAux), _vp]),
     "hn_search_topk": (_i32, [_vp, _vp, _i64, _i32, _vp, _vp, ctypes.POINTER(SearchOpts), _vp]),
     "hn_filter_survivors": (_i32, [_vp, _vp, _i64, _vp, _vp, _i64, ctypes.POINTER(_i64), _vp,
                                    ctypes.POINTER(SearchOpts), _vp]),

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "hn_pipeline.h"
 
@@ -21,6 +22,7 @@ struct Work {
     int seed_cfg = 0;
     int seed_precision = HN_PREC_BF16;  // HN_PREC_BF16 or HN_PREC_FP32
     int seed_width = 0;
+    Arena *fixed = nullptr;  // caller-provided scratch (no allocation), or NULL
     int shape = 16;  // tile shape of the argmax scan (16 or 32): decodes its groups
     const void *stream_x = nullptr;
     float *op32 = nullptr;
@@ -179,7 +181,8 @@ size_t stage_bytes(const hn_index *ix, int64_t q, const Work &W, bool window,
 // Prepare queries, run the plain-seed pass and compute thresholds.  With
 // `lower` the seed pass is skipped and L (and its entry, lower_idx, if not
 // NULL) is taken from the caller.  `window`: also the single-pass window
-// (W.win, W.win_scan, W.init_best) and the pair values.
+// (W.win, W.win_scan, W.init_best) and the pair values.  Scratch comes from
+// W.fixed when set (its capacity checked), else from the stream's arena.
 int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_search_opts &o,
                const double *lower, const int64_t *lower_idx, int64_t cap, Work &W,
                hipStream_t s, bool window = false, int topk = 0) {
@@ -192,9 +195,16 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
     W.cap = cap;
     size_t per_pair = 0;
     const size_t bytes = stage_bytes(ix, q, W, window, &per_pair) + (size_t)cap * per_pair;
-    Arena *ar = nullptr;
-    rc = arena_for((void *)s, bytes, &ar);
-    if (rc) return rc;
+    Arena *ar = W.fixed;
+    if (ar) {
+        if (bytes > ar->cap)
+            return fail(HN_ERR_INVALID_ARG, "search needs %zu bytes of scratch, %zu available",
+                        bytes, ar->cap);
+        ar->used = 0;
+    } else {
+        rc = arena_for((void *)s, bytes, &ar);
+        if (rc) return rc;
+    }
     W.op32 = ar->take<float>(qp * ix->kp);
     W.op16 = ar->take<uint16_t>(qp * ix->kb);
     if (W.precision != HN_PREC_FP32 && W.seed_precision != HN_PREC_FP32) W.op32 = nullptr;
@@ -424,7 +434,8 @@ __global__ void scatter_results(const int32_t *__restrict__ list, int64_t n,
 int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *out_idx,
                  double *out_sim, const hn_search_opts &o, const hn_search_aux *aux,
                  hn_search_stats *stats, hipStream_t s, const double *lower_in = nullptr,
-                 const int64_t *lower_idx_in = nullptr, Overflow *ov = nullptr) {
+                 const int64_t *lower_idx_in = nullptr, Overflow *ov = nullptr,
+                 Arena *fixed = nullptr) {
     const bool single = o.seed != HN_SEED_PLAIN && !lower_in;
     const int64_t cap =
         o.survivor_cap > 0
@@ -433,6 +444,7 @@ int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *o
                                           (int64_t)1 << 29)
                       : default_cap(ix->n, q));
     Work W;
+    W.fixed = fixed;
     int rc = stage_seed(ix, queries, q, o, lower_in, lower_idx_in, cap, W, s, single);
     if (rc) return rc;
     ScanArgs A = filter_args(ix, W, q, W.pairs, cap);
@@ -660,6 +672,101 @@ extern "C" int hn_search_top1(const hn_index *ix, const float *queries, int64_t 
         }
     }
     return HN_OK;
+}
+
+namespace hn {
+namespace {
+
+// Scratch of the allocation-free search: one copy of this array per GPU,
+// which each device that runs the library holds until the process ends.  In
+// host code its name is not a device address; the address comes from
+// hipGetSymbolAddress, once per device.
+constexpr size_t kNoAllocBytes = (size_t)HN_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device `dev`.
+int scratch_on(int dev, char **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(HN_ERR_UNSUPPORTED, "device %d", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(HN_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return HN_OK;
+}
+
+// A pair list shorter than this is not worth a search: the overflowing
+// queries would all take the exhaustive fallback.
+constexpr int64_t kNoAllocMinPairs = (int64_t)1 << 16;
+
+}  // namespace
+}  // namespace hn
+
+extern "C" int hn_search_top1_noalloc(const hn_index *ix, const float *queries, int64_t q,
+                                      int64_t *out_idx, double *out_sim,
+                                      const hn_search_opts *opts, const hn_search_aux *aux,
+                                      void *stream) {
+    clear_error();
+    if (!ix) return fail(HN_ERR_INVALID_ARG, "null index");
+    if (q < 0) return fail(HN_ERR_INVALID_ARG, "q must be >= 0");
+    if (q >= ((int64_t)1 << 31) - 4096) return fail(HN_ERR_UNSUPPORTED, "q must be < 2^31");
+    if (q > 0 && (!queries || !out_idx || !out_sim))
+        return fail(HN_ERR_INVALID_ARG, "null queries or outputs");
+    if (!aligned16(queries)) return fail(HN_ERR_INVALID_ARG, "queries must be 16-byte aligned");
+    int rc = validate_opts(ix, opts);
+    if (rc) return rc;
+    if (q == 0) return HN_OK;
+    hn_search_opts o = opts ? *opts : hn_search_opts{HN_PREC_FP32, HN_SEED_PLAIN, 0, 0, 0, -1.0};
+    if (o.seed != HN_SEED_PLAIN)
+        return fail(HN_ERR_UNSUPPORTED, "the allocation-free search takes the plain seed");
+    if (o.precision != HN_PREC_FP32 && o.precision != HN_PREC_BF16)
+        return fail(HN_ERR_UNSUPPORTED,
+                    "the allocation-free search scans in fp32 or bf16 (fp8 and int8 re-run "
+                    "overflowing queries with buffers of their own)");
+    int dev = 0;
+    HN_HIP(hipGetDevice(&dev));
+    if (dev != ix->device)
+        return fail(HN_ERR_INVALID_ARG, "the index lives on device %d, the current one is %d",
+                    ix->device, dev);
+    char *base = nullptr;
+    rc = scratch_on(dev, &base);
+    if (rc) return rc;
+    // size the call as search_batch will: everything but the pair list is
+    // fixed by (n, q) and the launch shapes; the pair list takes the rest
+    Work W;
+    rc = plan_stage(ix, q, o, W, false, 0);
+    if (rc) return rc;
+    size_t per_pair = 0;
+    const size_t fixed_bytes = stage_bytes(ix, q, W, false, &per_pair);
+    if (fixed_bytes + (size_t)kNoAllocMinPairs * per_pair > kNoAllocBytes)
+        return fail(HN_ERR_INVALID_ARG,
+                    "q = %lld queries against n = %lld entries need %zu bytes of scratch besides "
+                    "the survivor list; the allocation-free search has %zu: pass fewer queries "
+                    "per call",
+                    (long long)q, (long long)ix->n, fixed_bytes + (size_t)kNoAllocMinPairs * per_pair,
+                    kNoAllocBytes);
+    const int64_t fit = (int64_t)((kNoAllocBytes - fixed_bytes) / per_pair);
+    if (o.survivor_cap > fit)
+        return fail(HN_ERR_INVALID_ARG,
+                    "survivor_cap = %lld pairs does not fit the allocation-free scratch "
+                    "(at most %lld for this call)",
+                    (long long)o.survivor_cap, (long long)fit);
+    if (o.survivor_cap <= 0) o.survivor_cap = std::min<int64_t>(default_cap(ix->n, q), fit);
+    Arena fixed;
+    fixed.base = base;
+    fixed.cap = kNoAllocBytes;
+    return search_batch(ix, queries, q, out_idx, out_sim, o, aux, nullptr, (hipStream_t)stream,
+                        nullptr, nullptr, nullptr, &fixed);
 }
 
 extern "C" int hn_search_topk(const hn_index *ix, const float *queries, int64_t q, int32_t topk,

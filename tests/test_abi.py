@@ -66,12 +66,14 @@ def test_error_message_api_without_gpu():
     assert rc == _lib.HN_ERR_INVALID_ARG
 
 
-def test_memory_budget_argument_checks_without_gpu():
+def test_memory_budget_and_noalloc_argument_checks_without_gpu():
     from paper_2606_27280_amd import _lib
     L = _lib.lib()
     assert L.hn_memory_held() == 0
     assert L.hn_set_memory_budget(-1) == _lib.HN_ERR_INVALID_ARG
     assert L.hn_set_memory_budget(0) == _lib.HN_OK
+    rc = L.hn_search_top1_noalloc(None, None, 0, None, None, None, None, None)
+    assert rc == _lib.HN_ERR_INVALID_ARG and b"null" in L.hn_last_error()
     h = ctypes.c_void_p()
     rc = L.hn_build_index(ctypes.c_void_p(16), 10, 128, 8, 0.1, 1 << 1, None, ctypes.byref(h))
     assert rc == _lib.HN_ERR_INVALID_ARG and b"flags" in L.hn_last_error()

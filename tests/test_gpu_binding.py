@@ -71,6 +71,10 @@ def test_bad_arguments_raise_before_any_library_call(hn, monkeypatch):
                                                              device=d)[::2],
                                                  torch.empty(len(qs), dtype=torch.float64,
                                                              device=d))),
+        "noalloc narrow queries": lambda: ix.search_noalloc(q[:, :100].contiguous()),
+        "noalloc short out": lambda: ix.search_noalloc(
+            q, out=(torch.empty(1, dtype=torch.int64, device=d),
+                    torch.empty(1, dtype=torch.float64, device=d))),
         "topk narrow queries": lambda: ix.search_topk(q[:, :64].contiguous(), 3),
         "topk of 0": lambda: ix.search_topk(q, 0),
         "filter lower too short": lambda: ix.filter_survivors(
