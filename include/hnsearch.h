@@ -398,6 +398,15 @@ int hn_multi_search(hn_multi_plan *plan, const float *queries, int64_t *out_idx,
 int hn_multi_plan_info(const hn_multi_plan *plan, int64_t *total_queries, int64_t *work_items,
                        int32_t *scan_launches);
 
+/* Per-batch latency of the plan's last search, from device timestamps taken
+ * inside it (the constant-rate clock, 100 MHz on MI355X): ms[d] (host, n_db
+ * values) is the time from the start of the search's first kernel to the
+ * last write of database d's results; 0 for a database without queries.
+ * Every batch's results are written by the search's last kernel, so the
+ * values sit close to the whole search's time.  Synchronises `stream` (the
+ * stream the search ran on). */
+int hn_multi_batch_times(const hn_multi_plan *plan, double *ms, void *stream);
+
 void hn_multi_plan_free(hn_multi_plan *plan);
 
 /* ------------------------------------------------------------ device memory

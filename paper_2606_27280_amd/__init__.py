@@ -300,6 +300,14 @@ class MultiPlan:
                                               1 if use_graph else 0, _stream(stream)))
         return idx, sim
 
+    def batch_times(self, stream=None):
+        """hn_multi_batch_times: per database, milliseconds from the start of
+        the last search to the last write of its results (device clock)."""
+        n = len(self.q_counts)
+        ms = (ctypes.c_double * n)()
+        _lib.check(_lib.lib().hn_multi_batch_times(self._h, ms, _stream(stream)))
+        return list(ms)
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.lib().hn_multi_plan_free(self._h)

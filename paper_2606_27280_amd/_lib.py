@@ -92,6 +92,7 @@ SIGNATURES = {
     "hn_multi_plan_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
                                   ctypes.POINTER(_i32)]),
     "hn_multi_plan_free": (None, [_vp]),
+    "hn_multi_batch_times": (_i32, [_vp, ctypes.POINTER(_dbl), _vp]),
     "hn_set_memory_budget": (_i32, [_i64]),
     "hn_memory_held": (_i64, []),
     "hn_release_scratch": (_i32, [_vp]),

@@ -33,14 +33,19 @@ __global__ void copy_in(const float4 *__restrict__ q, const int64_t *__restrict_
     }
 }
 
+// The first kernel of a search: clears the flags and counters and records
+// the start on the constant-rate clock (ts[0]); ts[1 + d] collects database
+// d's last result write (finalize_kernel).
 __global__ void multi_reset(int32_t *qflag, int64_t total_pad, unsigned *redo_counts,
                             int n_groups, unsigned *item_ctrs, int n_ctrs,
-                            unsigned long long *counter) {
+                            unsigned long long *counter, unsigned long long *ts, int n_db) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t < total_pad) qflag[t] = 0;
     if (t < n_groups) redo_counts[t] = 0u;
     if (t < n_ctrs) item_ctrs[t] = 0u;
     if (t < 2) counter[t] = 0ull;
+    if (t == 0) ts[0] = (unsigned long long)wall_clock64();
+    if (t < n_db) ts[1 + t] = 0ull;
 }
 
 __global__ __launch_bounds__(256) void prep_multi(const PrepArgs *__restrict__ P,
@@ -90,6 +95,8 @@ struct hn_multi_plan {
     int *redo = nullptr;
     unsigned *redo_counts = nullptr;
     unsigned *item_ctrs = nullptr;  // per group: kXcds item counters of each scan pass
+    unsigned long long *ts = nullptr;  // [1 + n_db]: start, then per database its last write
+    bool fused = false;  // bf16 / int8: the filter's flushes rescore their pairs
     std::vector<MultiGroup> groups;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -118,10 +125,11 @@ int enqueue(hn_multi_plan *P, const float *queries, int64_t *out_idx, double *ou
             hipStream_t s) {
     const int ng = (int)P->groups.size();
     const int n_ctrs = 2 * kXcds * ng;
-    const int64_t reset_n = std::max<int64_t>(std::max<int64_t>(P->total_pad, 64), n_ctrs);
+    const int64_t reset_n = std::max<int64_t>(
+        std::max<int64_t>(std::max<int64_t>(P->total_pad, 64), n_ctrs), P->n_db);
     hipLaunchKernelGGL(multi_reset, dim3(blocks_for(reset_n)),
                        dim3(256), 0, s, P->qflag, P->total_pad, P->redo_counts, ng, P->item_ctrs,
-                       n_ctrs, P->counter);
+                       n_ctrs, P->counter, P->ts, P->n_db);
     hipLaunchKernelGGL(copy_in, dim3((unsigned)std::min<int64_t>(blocks_for(P->total_q * 32), 8192)),
                        dim3(256), 0, s, reinterpret_cast<const float4 *>(queries), P->o2p,
                        P->total_q, reinterpret_cast<float4 *>(P->q_buf));
@@ -169,7 +177,7 @@ int enqueue(hn_multi_plan *P, const float *queries, int64_t *out_idx, double *ou
     R.q = P->total_pad;
     R.db = P->dbref;
     R.gdb = P->gdb;
-    {
+    if (!P->fused) {
         ProfScope prof_(s, "multi_rescore");
         if (P->precision == HN_PREC_FP32)
             hipLaunchKernelGGL(rescore_kernel<0>, dim3(2048), dim3(256), 0, s, R);
@@ -203,6 +211,7 @@ int enqueue(hn_multi_plan *P, const float *queries, int64_t *out_idx, double *ou
     Z.out_sim = out_sim;
     Z.db = P->dbref;
     Z.gdb = P->gdb;
+    Z.ts_end = P->ts + 1;
     hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(P->total_pad)), dim3(256), 0, s, Z);
     HN_HIP(hipGetLastError());
     return HN_OK;
@@ -339,7 +348,7 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
                  o_o2p = add(std::max<int64_t>(total_q, 1), 8),
                  o_sa = add(n_db, sizeof(ScanArgs)), o_sf = add(n_db, sizeof(ScanArgs)),
                  o_seed = add(n_db, sizeof(SeedArgs)), o_prep = add(n_db, sizeof(PrepArgs)),
-                 o_db = add(n_db, sizeof(DbRef));
+                 o_db = add(n_db, sizeof(DbRef)), o_ts = add(n_db + 1, 8);
     if (dev_alloc(&P->mem, bytes) != hipSuccess) {
         (void)hipGetLastError();
         plan_destroy(P);
@@ -374,6 +383,9 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
     P->seeds = reinterpret_cast<SeedArgs *>(m + o_seed);
     P->preps = reinterpret_cast<PrepArgs *>(m + o_prep);
     P->dbref = reinterpret_cast<DbRef *>(m + o_db);
+    P->ts = reinterpret_cast<unsigned long long *>(m + o_ts);
+    // must match the tiles compiled with kFused (every bf16 and int8 tile)
+    P->fused = o.precision == HN_PREC_BF16 || o.precision == HN_PREC_INT8;
 
     // host tables
     std::vector<ScanArgs> sa(n_db), sf(n_db);
@@ -413,6 +425,20 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
         A.counter = P->counter;
         A.cap = cap;
         A.qflag = P->qflag;
+        if (P->fused) {
+            // the filter's flushes rescore their pairs (float32 re-check,
+            // canonical float64 sim, running key) with this database's rows;
+            // pairs carry padded query positions, which index the padded
+            // query copy, the re-check thresholds and the keys directly
+            A.psim = P->psim;
+            A.best_key = P->best_key;
+            A.rs_queries = P->q_buf;
+            A.rs_rows = ix->rows;
+            A.rs_major32 = ix->major32;
+            A.rs_thr32 = P->thr32;
+            A.rs_kp = ix->kp;
+            A.rs_k = ix->k;
+        }
         sf[d] = A;
 
         SeedArgs S;
@@ -529,6 +555,24 @@ extern "C" int hn_multi_plan_info(const hn_multi_plan *plan, int64_t *total_quer
     if (total_queries) *total_queries = plan->total_q;
     if (work_items) *work_items = plan->total_items;
     if (scan_launches) *scan_launches = 2 * (int32_t)plan->groups.size();
+    return HN_OK;
+}
+
+extern "C" int hn_multi_batch_times(const hn_multi_plan *plan, double *ms, void *stream) {
+    clear_error();
+    if (!plan || !ms) return fail(HN_ERR_INVALID_ARG, "null argument");
+    std::vector<unsigned long long> ts((size_t)plan->n_db + 1);
+    hipStream_t s = (hipStream_t)stream;
+    HN_HIP(hipMemcpyAsync(ts.data(), plan->ts, sizeof(unsigned long long) * ts.size(),
+                          hipMemcpyDeviceToHost, s));
+    HN_HIP(hipStreamSynchronize(s));
+    int khz = 0;
+    HN_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, plan->device));
+    if (khz <= 0) return fail(HN_ERR_DEVICE, "no constant-rate clock rate");
+    for (int d = 0; d < plan->n_db; ++d)
+        ms[d] = ts[1 + d] >= ts[0] && ts[1 + d] != 0ull
+                    ? (double)(ts[1 + d] - ts[0]) / (double)khz
+                    : 0.0;
     return HN_OK;
 }
 

@@ -643,7 +643,10 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs R) {
         double s = -INFINITY;
         if (keep) {
             s = sim64(qv, rows + (int64_t)pr.y * kDim);
-            atomicMax(&R.best_key[pr.x], key_of(s));
+            // best_key starts at the seed's key and only grows: most
+            // survivors are below it and need no atomic
+            const unsigned long long kk = key_of(s);
+            if (kk > R.best_key[pr.x]) atomicMax(&R.best_key[pr.x], kk);
         }
         R.psim[p] = s;
     }
@@ -776,6 +779,8 @@ struct FinalArgs {
     unsigned long long *n_flagged;
     const DbRef *db;     // multi-database (or NULL): F.q counts padded
     const int32_t *gdb;  //   positions; outputs go to out_base + local
+    unsigned long long *ts_end;  // multi-database: per database, the latest
+                                 // constant-rate clock of its result writes
 };
 
 __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs F) {
@@ -797,6 +802,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs F) {
     if (F.aux.threshold) F.aux.threshold[o] = F.thr ? F.thr[i] : (float)NAN;
     if (F.aux.slack) F.aux.slack[o] = F.slack ? F.slack[i] : (double)NAN;
     if (F.n_flagged && F.qflag[i]) atomicAdd(F.n_flagged, 1ull);
+    if (F.ts_end) atomicMax(&F.ts_end[F.gdb[i]], (unsigned long long)wall_clock64());
 }
 
 // ------------------------------------------------------------ exact top-k

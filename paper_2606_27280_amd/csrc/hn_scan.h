@@ -414,7 +414,10 @@ __device__ __forceinline__ void flush_pairs(const ScanArgs &A, EmitBuf &B) {
                 double sv = -INFINITY;
                 if (keep) {
                     sv = sim64(qv, A.rs_rows + (int64_t)pr.y * kDim);
-                    atomicMax(&A.best_key[pr.x], key_of(sv));
+                    // best_key starts at the seed's key and only grows: most
+                    // survivors are below it and need no atomic
+                    const unsigned long long kk = key_of(sv);
+                    if (kk > A.best_key[pr.x]) atomicMax(&A.best_key[pr.x], kk);
                 }
                 A.psim[pos] = sv;
                 if (A.cnt) atomicAdd(&A.cnt[pr.x], 1);

@@ -164,3 +164,108 @@ def test_multi_rejects(hn):
     plan.close()
     ix64.close()
     ix16.close()
+
+
+def _self_queries(db, k, alpha, count):
+    """q = x_i, rows whose stored minor norm exceeds sqrt(alpha) first."""
+    x = db.astype(np.float64)
+    over = np.nonzero((x[:, k:] ** 2).sum(1) > alpha)[0]
+    rest = np.setdiff1d(np.arange(len(db)), over)
+    pick = np.concatenate([over[: count // 2], rest])[:count]
+    return db[pick].copy()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "int8"])
+def test_multi_self_and_minor_heavy_queries(hn, precision):
+    """Exact self-queries (including rows with a float32 minor-norm excess)
+    and queries whose minor block is scaled up (the bound needs the slack's
+    norm term) in every database of a plan: results equal the oracle's."""
+    dbs = []
+    for db, qs, k, a in _dbs(7400):
+        if len(qs):
+            heavy = qs.astype(np.float64)
+            heavy[:, k:] *= 2.0
+            qs = np.concatenate([qs, heavy.astype(np.float32),
+                                 _self_queries(db, k, a, min(len(db), 6))])
+        dbs.append((db, qs, k, a))
+    ref = _reference(dbs)
+    ixs = [hn.Index(dev(db), k, a) for db, _, k, a in dbs]
+    qs = np.concatenate([q for _, q, _, _ in dbs])
+    say("multi plan with self and minor-heavy queries: %d queries, %s" % (len(qs), precision))
+    plan = hn.MultiPlan(ixs, [len(q) for _, q, _, _ in dbs], precision=precision)
+    for use_graph in (False, True):
+        idx, sim = plan.search(dev(qs), use_graph=use_graph)
+        _check(idx, sim, ref, "%s self/heavy graph=%s" % (precision, use_graph))
+    plan.close()
+    for ix in ixs:
+        ix.close()
+
+
+def test_multi_batch_times_from_the_replay(hn):
+    """Device timestamps inside the replayed graph: one time per database,
+    positive where the database has queries, 0 where it has none, and no
+    later than the search's own length."""
+    import torch
+    dbs = _dbs(7500)
+    ixs = [hn.Index(dev(db), k, a) for db, _, k, a in dbs]
+    counts = [len(q) for _, q, _, _ in dbs]
+    plan = hn.MultiPlan(ixs, counts, precision="bf16")
+    dq = dev(np.concatenate([q for _, q, _, _ in dbs]))
+    out = (torch.empty(len(dq), dtype=torch.int64, device="cuda:0"),
+           torch.empty(len(dq), dtype=torch.float64, device="cuda:0"))
+    plan.search(dq, use_graph=True, out=out)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    plan.search(dq, use_graph=True, out=out)
+    b.record()
+    torch.cuda.synchronize()
+    total = a.elapsed_time(b)
+    ms = plan.batch_times()
+    say("batch times (ms): %s; whole replay %.4f ms" % (["%.4f" % v for v in ms], total))
+    assert len(ms) == len(counts)
+    for c, v in zip(counts, ms):
+        if c:
+            assert 0.0 < v <= total * 1.05 + 0.01
+        else:
+            assert v == 0.0
+    _check(*out, _reference(dbs), "timed replay")
+    plan.close()
+    for ix in ixs:
+        ix.close()
+
+
+def test_autotuner_single_and_multi(hn, tmp_path):
+    """The tuner times every candidate launch shape, rejects any shape that
+    changes a result (all are bit-identical by construction), keeps the
+    fastest and caches it."""
+    from paper_2606_27280_amd.autotune import Tuner
+    import hn_inputs
+    dbs = _dbs(7600)
+    ixs = [hn.Index(dev(db), k, a) for db, _, k, a in dbs]
+    counts = [len(q) for _, q, _, _ in dbs]
+    dq = dev(np.concatenate([q for _, q, _, _ in dbs]))
+    t = Tuner(str(tmp_path / "tune.json"))
+    say("tune multi")
+    best, table = t.tune_multi(ixs, counts, dq, precision="bf16", query_tiles=(1, 2),
+                               chunk_blocks=(0, 16), reps=2)
+    assert set(table) == {(1, 0), (1, 16), (2, 0), (2, 16)}
+    assert best in table and table[best] == min(table.values())
+    w = hn_inputs.workload(1)
+    db = w.db()
+    qs = dev(w.queries(db))
+    ix = hn.Index(dev(db), w.k, w.alpha)
+    say("tune single")
+    best1, table1 = t.tune(ix, qs, precision="fp32", query_tiles=(1, 2), chunk_blocks=(0, 32),
+                           reps=2)
+    assert len(table1) == 4 and table1[best1] == min(table1.values())
+    import torch
+    t2 = Tuner(str(tmp_path / "tune.json"))
+    assert t2.lookup(torch.cuda.get_device_name(0), ix.n, ix.k, "fp32", len(qs)) == best1
+    i_b, s_b = ix.search(qs, query_tiles=best1[0], chunk_blocks=best1[1])
+    i_0, s_0 = ix.search(qs)
+    assert torch.equal(i_b, i_0) and torch.equal(s_b, s_0)
+    ix.close()
+    for x in ixs:
+        x.close()

@@ -620,14 +620,24 @@ def test_soft_beta_mode(hn, frac):
     L = sa["seed_sim"].cpu().numpy()
     assert (ss <= es).all()
     assert (sa["survivors"].cpu().numpy() <= ea["survivors"].cpu().numpy()).all()
+    # Algorithm 1 with beta in the skip test (the oracle's running-best form)
+    soft = oracle.bnb_top1(db, qs, w.k, w.alpha, beta=beta)
+    assert (soft["sim"] <= es).all()
     for qi in range(len(qs)):
         assert ss[qi] == oracle.sim(qs[qi], db[si[qi]])
         must = oracle.survivor_list(db, qs[qi], w.k, beta, L[qi] + 2.0 ** -40)
         if len(must):
             best_must = max(oracle.sim(qs[qi], db[j]) for j in must)
             assert ss[qi] >= best_must
+        # both results r are fixed points of the weakened bound: no entry
+        # whose major score plus beta reaches r beats it
+        for r in (ss[qi], soft["sim"][qi]):
+            reach = oracle.survivor_list(db, qs[qi], w.k, beta, r + 2.0 ** -40)
+            if len(reach):
+                assert max(oracle.sim(qs[qi], db[j]) for j in reach) <= r
     recall = float((si == ei).mean())
-    say("recall@1 at beta=%g: %.3f" % (beta, recall))
+    say("recall@1 at beta=%g: GPU (seed threshold) %.3f, Algorithm 1 (running best) %.3f" % (
+        beta, recall, float((soft["idx"] == ei).mean())))
     ix.close()
 
 
