@@ -14,9 +14,10 @@ timed steps) and the CPU oracle timed on a bounded sample.
 --workload 4: 64 databases (N_d log-uniform in [4096, 2^21], K_d in {8, 16},
 alpha_d in {1/32, 1/8}) with ragged query batches (Q_d log-uniform in
 [1, 4096]), searched as one multi-database plan replayed as a HIP graph;
-reports whole-set queries/s, the per-database batch latency p50/p99 (each
-batch alone through its own plan and graph), the same queries as sequential
-single-database calls, and exactness against them.
+reports whole-set queries/s, the per-database batch latency p50/p99 from
+device timestamps inside the replayed graph (and each batch alone through its
+own plan), the same queries as sequential single-database calls, and
+exactness against them.
 
 Other workloads: --workload 3 (N = 4M, K = 8, alpha = 1/32, Q = 65,536; the
 precision form) and --workload 5 (N = 4M, K = 16, alpha = 1/8, Q = 65,536
@@ -35,6 +36,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "exact top-1 queries/s @N=1M,K=16,α=1/8 vs GPU brute force; % entries pruned"
+METRICS = {
+    2: METRIC,
+    3: "exact top-1 queries/s @N=4M,K=8,α=1/32, precision forms vs GPU brute force; "
+       "% entries pruned",
+    4: "exact top-1 queries/s, 64 databases with ragged query batches (one plan, HIP graph); "
+       "per-batch latency p50/p99",
+    5: "exact top-1 queries/s @N=4M,K=16,α=1/8, learned vs plain seed; % entries pruned",
+}
+VALU_PEAK_TLOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # vector lane-ops/s: CUs x SIMDs x lanes x clock
 PEAK = {  # MI355X published dense peaks
     "hbm_gbs": 8000.0,
     "fp32_mfma_tflops": 157.3,
@@ -74,6 +84,12 @@ def parse():
     ap.add_argument("--table3", action="store_true",
                     help="the (K, alpha) grid of the paper's Table 3 at N = 500,000")
     ap.add_argument("--chunk-blocks", type=int, default=0)
+    ap.add_argument("--seed-scan", default="bf16", choices=["bf16", "fp32"],
+                    help="precision of the plain seed's argmax scan (fp32: the all-float32 "
+                         "search)")
+    ap.add_argument("--seed-sweep", action="store_true",
+                    help="learned seed against the plain seed and the window-only form at "
+                         "N = 2^20 over cluster counts 128 / 512 / 4096 / 16384")
     ap.add_argument("--seed", default=None, choices=["plain", "learned", "window"],
                     help="timed seed form (default: learned for workload 5, else plain)")
     ap.add_argument("--epochs", type=int, default=4, help="seed-model training epochs")
@@ -365,6 +381,146 @@ def build_seed_model(hn, ix, w, db, dev, torch):
     return rep
 
 
+def _seed_forms(hn, ix, d_q, n, k, steps, torch, plain_cap):
+    """The three seed forms on bf16 scans: queries/s, bound, first-pass
+    survivors, bytes of the prefix stream and of the survivor pairs, and
+    whether the result equals the plain form's."""
+    Q = d_q.shape[0]
+    ref = None
+    forms = {}
+    for sf, cap in (("plain", plain_cap), ("plain_default_cap", 0), ("learned", 0),
+                    ("window", 0)):
+        seed = "plain" if sf.startswith("plain") else sf
+        i2, s2, a2, st = ix.search(d_q, precision="bf16", seed=seed, survivor_cap=cap, aux=True,
+                                   stats=True)
+        if ref is None:
+            ref = (i2.clone(), s2.clone())
+        t2, _ = timed(lambda: ix.search(d_q, precision="bf16", seed=seed, survivor_cap=cap,
+                                        out=(i2, s2)), steps, 1, torch)
+        surv = float(a2["survivors"].double().mean())
+        forms[sf] = {"queries_per_s": round(Q * steps / t2, 1),
+                     "survivors_per_query": round(surv, 2),
+                     "pruned_pct": round(100.0 * (1.0 - surv / n), 4),
+                     "mean_L": None if sf == "window" else round(float(torch.nan_to_num(
+                         a2["seed_sim"], neginf=float("nan")).nanmean()), 4),
+                     "overflow_queries": st["overflow_queries"],
+                     "bytes": {"stream": (2 if seed == "plain" else 1) * n * k * 2,
+                               "pairs": int((8 if seed == "plain" else 12) * surv * Q)},
+                     "same_result": bool(torch.equal(i2, ref[0]) and torch.equal(s2, ref[1]))}
+    return forms
+
+
+def _train_seed(hn, ix, d_qt, seed, torch):
+    t0 = time.perf_counter()
+    import hn_inputs
+    dev = d_qt.device
+    anchors = ix.kmeanspp(512, torch.from_numpy(hn_inputs.uniform_draws(512, seed + 0x300)).to(dev))
+    labels = ix.seed_labels(anchors, d_qt)
+    params = torch.from_numpy(hn_inputs.mlp_init(seed + 0x201)).to(dev)
+    losses = hn.seed_train(params, d_qt, labels, batch=1024, epochs=4, lr=2e-3)
+    ix.set_seed_model(params, anchors)
+    torch.cuda.synchronize()
+    ls = losses.cpu().numpy()
+    return {"seed_model_build_s": round(time.perf_counter() - t0, 2),
+            "loss_first_epoch": round(float(ls[:len(ls) // 4].mean()), 3),
+            "loss_last_epoch": round(float(ls[-(len(ls) // 4):].mean()), 3)}
+
+
+def bench_seed_sweep(args):
+    """Where the learned seed could pay.  (1) N = 2^20, K = 16, alpha = 1/8
+    over cluster counts 128, 512, 4,096 and 16,384 (10,000 perturbed queries,
+    512 k-means++ anchors, 200,000 training queries, 4 epochs).  (2) The
+    small-Q streaming regime: N = 2^24 (65,536 clusters, drawn on the device
+    as in the streaming workload), 32 queries, where one scan pass less could
+    outweigh a weaker bound.  For each: the learned single pass, the
+    window-only single pass and the plain two-pass seed (with a survivor list
+    large enough for every query, and with the default list, whose
+    overflowing queries take the exhaustive fallback), all on bf16 scans and
+    all exact (every form's result equals the plain form's)."""
+    import math
+
+    import torch
+
+    import hn_inputs
+    import paper_2606_27280_amd as hn
+    dev = torch.device("cuda:0")
+    n, k, alpha, Q = 1 << 20, 16, 1 / 8, args.queries or 10000
+    rows = []
+    for nc in (128, 512, 4096, 16384):
+        seed = hn_inputs.DB_SEED_BASE + 0x50 + int(math.log2(nc))
+        db = hn_inputs.make_db(n, k, alpha, nc, seed)
+        qs = hn_inputs.make_queries(db, k, alpha, Q, 0, seed + hn_inputs.QUERY_SEED_OFFSET)
+        qt = hn_inputs.make_queries(db, k, alpha, 200000, 0, seed + 0x200)
+        ix = hn.Index(torch.from_numpy(db).to(dev), k, alpha)
+        d_q, d_qt = torch.from_numpy(qs).to(dev), torch.from_numpy(qt).to(dev)
+        row = {"n": n, "clusters": nc, "queries": Q}
+        row.update(_train_seed(hn, ix, d_qt, seed, torch))
+        row["forms"] = _seed_forms(hn, ix, d_q, n, k, args.steps, torch, Q * 16384)
+        log(json.dumps(row))
+        rows.append(row)
+        ix.close()
+        del d_q, d_qt
+    # small-Q streaming regime
+    n2, nc2, q2 = 1 << 24, 1 << 16, 32
+    seed = hn_inputs.DB_SEED_BASE + 0x60
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    centres = torch.randn((nc2, 128), generator=g, device=dev)
+    ids = torch.randint(0, nc2, (n2,), generator=g, device=dev)
+    raw = centres[ids]
+    raw.add_(torch.randn((n2, 128), generator=g, device=dev), alpha=0.3)
+    db2 = hn.hn_layer(raw, k, alpha)
+    del raw, centres, ids
+
+    def perturbed(m):
+        r = torch.randint(0, n2, (m,), generator=g, device=dev)
+        return hn.hn_layer(db2[r] + 0.05 * torch.randn((m, 128), generator=g, device=dev), k,
+                           alpha)
+
+    d_q2, d_qt2 = perturbed(q2), perturbed(200000)
+    ix = hn.Index(db2, k, alpha)
+    row = {"n": n2, "clusters": nc2, "queries": q2}
+    row.update(_train_seed(hn, ix, d_qt2, seed, torch))
+    row["forms"] = _seed_forms(hn, ix, d_q2, n2, k, args.steps * 4, torch, q2 * 1 << 20)
+    log(json.dumps(row))
+    ix.close()
+    print(json.dumps({"metric": "learned seed vs plain seed (exact top-1 queries/s, first-pass "
+                                "survivors, bytes) over cluster counts and at small Q",
+                      "unit": "queries/s", "n_gpus": 1, "dtype": "bf16", "data": "synthetic",
+                      "config": {"workload": "hn_seed_sweep", "k": k, "alpha": alpha,
+                                 "anchors": 512, "train_queries": 200000, "epochs": 4},
+                      "rows": rows, "small_q": row}), flush=True)
+
+
+def seed_oracle_check(db, qs, w, aux_of, n_sample=64):
+    """The seeds' bounds judged by the oracle on a strided sample of queries:
+    the exact seed-threshold survivor set |S(q, L)| = |{i : dot_K + alpha >=
+    L}| at the plain seed's L and at the learned seed's L (the entries a
+    filter with that bound must keep), and whether the plain seed's GPU
+    survivor count lies between the oracle's exact sets at its own L."""
+    import numpy as np
+
+    import oracle
+    sample = np.arange(0, len(qs), max(1, len(qs) // n_sample))[:n_sample]
+    out = {"sample_queries": int(len(sample))}
+    for sf in ("plain", "learned"):
+        a = aux_of[sf]
+        L = a["seed_sim"].cpu().numpy()[sample]
+        L = np.where(np.isfinite(L), L, -np.inf)
+        at_L, _ = oracle.survivor_counts(db, qs[sample], w.k, w.alpha, L, L)
+        out[sf] = {"mean_L": round(float(np.mean(L)), 5),
+                   "oracle_survivors_per_query_at_L": round(float(at_L.mean()), 2),
+                   "oracle_pruned_pct_at_L": round(float(100.0 * (1.0 - at_L.mean() / len(db))), 4)}
+    a = aux_of["plain"]
+    L = a["seed_sim"].cpu().numpy()[sample]
+    eps = a["slack"].cpu().numpy()[sample]
+    lo, hi = oracle.survivor_counts(db, qs[sample], w.k, w.alpha, L - 2 * eps - 2.0 ** -20,
+                                    L + 2.0 ** -40)
+    got = a["survivors"].cpu().numpy()[sample]
+    out["plain_gpu_survivors_within_oracle_sets"] = bool(((hi <= got) & (got <= lo)).all())
+    return out
+
+
 def timed(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -476,6 +632,13 @@ def bench_batched(args):
     sec = gpu_time(step, args.steps, torch)
     qps = Q / sec
     log("multi plan (graph): %.3f ms per set, %.0f queries/s" % (1e3 * sec, qps))
+    # per-batch latency inside the replayed graph: device timestamps from the
+    # search's first kernel to the last write of each database's results
+    in_replay = []
+    for _ in range(max(3, args.steps)):
+        step()
+        in_replay.extend(v for v, c in zip(plan.batch_times(), counts) if c)
+    in_replay = np.array(in_replay)
     # kernel times of one eager pass
     with hn.profile() as prof:
         plan.search(dq, use_graph=False)
@@ -506,7 +669,7 @@ def bench_batched(args):
     exact = bool(torch.equal(s_idx, idx) and torch.equal(s_sim, sim))
     ssec = gpu_time(singles, max(1, args.steps // 2), torch)
     log("one call per database: %.3f ms per set; identical=%s" % (1e3 * ssec, exact))
-    # per-batch latency: each database's batch alone, own plan, graph
+    # each database's batch alone: its own plan, graph
     lat = []
     for ix, q0, c in zip(ixs, np.cumsum([0] + counts[:-1]), counts):
         if not c:
@@ -520,7 +683,7 @@ def bench_batched(args):
         p1.close()
     lat = np.array(lat) * 1e3
     res = {
-        "metric": METRIC,
+        "metric": METRICS[4],
         "value": round(qps, 1),
         "unit": "queries/s",
         "n_gpus": 1,
@@ -542,9 +705,17 @@ def bench_batched(args):
         "plan": plan.info(),
         "roofline": roofline,
         "kernels": kernels,
-        "per_batch_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                                 "p99": round(float(np.percentile(lat, 99)), 4),
-                                 "max": round(float(lat.max()), 4), "batches": int(len(lat))},
+        "per_batch_latency_ms": {"p50": round(float(np.percentile(in_replay, 50)), 4),
+                                 "p99": round(float(np.percentile(in_replay, 99)), 4),
+                                 "max": round(float(in_replay.max()), 4),
+                                 "samples": int(len(in_replay)),
+                                 "how": "device clock (100 MHz) inside the replayed graph: from "
+                                        "the search's first kernel to the last write of the "
+                                        "batch's results"},
+        "per_batch_alone_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                               "p99": round(float(np.percentile(lat, 99)), 4),
+                               "max": round(float(lat.max()), 4), "batches": int(len(lat)),
+                               "how": "each batch alone through its own one-database plan"},
         "sequential_calls": {"queries_per_s": round(Q / ssec, 1), "ms_per_set": round(1e3 * ssec, 4)},
         "speedup_vs_sequential": round(ssec / sec, 2),
         "exact_vs_single": exact,
@@ -578,6 +749,9 @@ def main():
     if args.table3:
         bench_table3(args)
         return
+    if args.seed_sweep:
+        bench_seed_sweep(args)
+        return
     import numpy as np
     import torch
 
@@ -604,7 +778,7 @@ def main():
     if args.workload == 5 or seed == "learned":
         seed_report = build_seed_model(hn, ix, w, db, dev, torch)
     kw = dict(precision=args.precision, query_tiles=args.query_tiles,
-              chunk_blocks=args.chunk_blocks, seed=seed)
+              chunk_blocks=args.chunk_blocks, seed=seed, seed_scan=args.seed_scan)
 
     def step():
         ix.search(d_q, out=(idx, sim), **kw)
@@ -633,9 +807,15 @@ def main():
     peak = PEAK[{"f32": "fp32_mfma_tflops", "bf16": "bf16_mfma_tflops",
                  "fp8": "fp8_mfma_tflops", "int8": "int8_mfma_tops"}[dom.rsplit("_", 1)[1]]]
     achieved = flops / avg_s / 1e12
+    # the epilogue's floor: at least half a vector lane-op per (query, entry)
+    # score (one three-input max takes two new scores per lane)
+    valu_tlops = 0.5 * Q * w.n / per_step / avg_s / 1e12
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
                 "unit": "TOP/s" if dom.endswith("int8") else "TFLOP/s",
                 "frac": round(achieved / peak, 4),
+                "valu_frac": round(valu_tlops / VALU_PEAK_TLOPS, 4),
+                "valu": {"lane_ops_per_pair": 0.5, "achieved_tlops": round(valu_tlops, 3),
+                         "peak_tlops": round(VALU_PEAK_TLOPS, 2)},
                 "traffic": measured_traffic(dom, w.name) if per_step == 1 else None,
                 "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
                                 "copy-calibrated)",
@@ -690,13 +870,15 @@ def main():
 
     forms = {}
     if not args.no_forms:
-        for prec in ("fp32", "bf16", "fp8", "int8"):
-            if prec == args.precision:
-                forms[prec] = round(qps, 1)
+        for prec, ss in (("fp32", "bf16"), ("fp32", "fp32"), ("bf16", "bf16"),
+                         ("fp8", "bf16"), ("int8", "bf16")):
+            name = prec if ss == "bf16" else prec + "_seed_scan_fp32"
+            if prec == args.precision and ss == args.seed_scan:
+                forms[name] = round(qps, 1)
                 continue
-            s2, _ = timed(lambda: ix.search(d_q, out=(idx, sim), precision=prec, seed=seed),
-                          args.steps, 2, torch)
-            forms[prec] = round(Q * args.steps / s2, 1)
+            s2, _ = timed(lambda: ix.search(d_q, out=(idx, sim), precision=prec, seed=seed,
+                                            seed_scan=ss), args.steps, 2, torch)
+            forms[name] = round(Q * args.steps / s2, 1)
         log("forms: %s" % forms)
     beta_sweep = []
     if args.beta_sweep:
@@ -725,26 +907,32 @@ def main():
                     "first_column_equals_top1": first_equal}
         log("top-%d: %s" % (kt, topk_res))
     seed_forms = {}
+    seed_oracle = None
     if seed_report is not None:
         # every seed form at the timed precision: queries/s, first-pass
         # survivors per query, exactness against the timed form
+        aux_of = {}
         for sf in ("plain", "learned", "window"):
             log("seed form %s" % sf)
             kws = dict(kw, seed=sf)
             i2, s2_, a2 = ix.search(d_q, aux=True, **kws)
+            aux_of[sf] = a2
             same = bool(torch.equal(i2, idx) and torch.equal(s2_, sim))
             t2, _ = timed(lambda: ix.search(d_q, out=(i2, s2_), **kws), args.steps, 1, torch)
+            surv_sf = float(a2["survivors"].double().mean())
             seed_forms[sf] = {"queries_per_s": round(Q * args.steps / t2, 1),
-                              "survivors_per_query": round(float(
-                                  a2["survivors"].double().mean()), 2),
+                              "survivors_per_query": round(surv_sf, 2),
+                              "pruned_pct": round(100.0 * (1.0 - surv_sf / w.n), 4),
                               "mean_seed_sim": round(float(torch.nan_to_num(
                                   a2["seed_sim"], neginf=float("nan")).nanmean()), 5)
                               if sf != "window" else None,
                               "same_result": same}
         log("seed forms: %s" % seed_forms)
+        seed_oracle = seed_oracle_check(db, qs, w, aux_of)
+        log("seed bounds judged by the oracle: %s" % seed_oracle)
 
     res = {
-        "metric": METRIC,
+        "metric": METRICS.get(args.workload, METRIC),
         "value": round(qps, 1),
         "unit": "queries/s",
         "n_gpus": 1,
@@ -760,6 +948,7 @@ def main():
         "config": {"workload": w.name, "n": w.n, "d": 128, "k": w.k, "alpha": w.alpha,
                    "queries": Q, "query_mix": "%d perturbed + %d fresh" % (w.n_perturbed, w.n_fresh),
                    "clusters": w.n_clusters, "precision": args.precision, "seed": seed,
+                   "seed_scan": args.seed_scan if seed == "plain" else None,
                    "rescoring": "f64"},
         "pruned_pct": round(pruned_pct, 4),
         "survivors_per_query": round(float(surv.mean()), 2),
@@ -774,6 +963,7 @@ def main():
     if seed_report is not None:
         res["seed_model"] = seed_report
         res["seed_forms"] = seed_forms
+        res["seed_oracle"] = seed_oracle
     if beta_sweep:
         res["beta_sweep"] = beta_sweep
     if topk_res is not None:

@@ -174,11 +174,17 @@ int hn_index_info(const hn_index *ix, int64_t *n, int32_t *k, double *alpha,
  *   queries  device, float32 [q][128]; q >= 0 (q = 0 is a no-op).
  *   out_idx  device, int64 [q];  out_sim  device, double [q].
  *   opts     NULL = defaults.  aux, stats: NULL allowed; a non-NULL stats
- *            makes the call synchronise `stream`, and so do the fp8 scan and
- *            the single-pass seeds (once per query batch): their queries whose
- *            survivors overflow the pair list are searched again by a float32
- *            filter pass seeded with the best candidate they reached.  Other
- *            forms finish such queries with an exhaustive float64 pass.
+ *            makes the call synchronise `stream`.  The survivor list holds
+ *            max(4096, n / 256) pairs per query by default (at least 2^20, at
+ *            most 2^28 in all).  With the plain seed on the FP32 and BF16
+ *            scans the call never synchronises: queries whose survivors
+ *            overflow the list are finished by an exhaustive float64 pass
+ *            (slow when many do: raise survivor_cap for such data).  The fp8
+ *            and int8 scans and the single-pass seeds keep many more pairs:
+ *            they synchronise once per query batch and search their
+ *            overflowing queries again by a float32 filter pass seeded with
+ *            the best candidate each reached, with a list sized from the
+ *            first pass's pair count (the plain seed) or the default rule.
  * A query with a non-finite component gets idx -1 and sim NaN.
  */
 int hn_search_top1(const hn_index *ix, const float *queries, int64_t q, int64_t *out_idx,

@@ -96,7 +96,7 @@ struct hn_multi_plan {
     unsigned *redo_counts = nullptr;
     unsigned *item_ctrs = nullptr;  // per group: kXcds item counters of each scan pass
     unsigned long long *ts = nullptr;  // [1 + n_db]: start, then per database its last write
-    bool fused = false;  // bf16 / int8: the filter's flushes rescore their pairs
+    bool fused = false;  // all but fp8: the filter's flushes rescore their pairs
     std::vector<MultiGroup> groups;
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -384,8 +384,9 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
     P->preps = reinterpret_cast<PrepArgs *>(m + o_prep);
     P->dbref = reinterpret_cast<DbRef *>(m + o_db);
     P->ts = reinterpret_cast<unsigned long long *>(m + o_ts);
-    // must match the tiles compiled with kFused (every bf16 and int8 tile)
-    P->fused = o.precision == HN_PREC_BF16 || o.precision == HN_PREC_INT8;
+    // must match the tiles compiled with kFused (every float32, bf16 and
+    // int8 tile)
+    P->fused = o.precision != HN_PREC_FP8;
 
     // host tables
     std::vector<ScanArgs> sa(n_db), sf(n_db);
@@ -434,10 +435,12 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
             A.best_key = P->best_key;
             A.rs_queries = P->q_buf;
             A.rs_rows = ix->rows;
-            A.rs_major32 = ix->major32;
-            A.rs_thr32 = P->thr32;
-            A.rs_kp = ix->kp;
-            A.rs_k = ix->k;
+            if (o.precision != HN_PREC_FP32) {  // low precision: float32 re-check first
+                A.rs_major32 = ix->major32;
+                A.rs_thr32 = P->thr32;
+                A.rs_kp = ix->kp;
+                A.rs_k = ix->k;
+            }
         }
         sf[d] = A;
 

@@ -506,10 +506,10 @@ int check_precision(const hn_index *ix, int precision) {
     return HN_OK;
 }
 
-// Survivor-list capacity of the two-pass search: max(2048, n / 512) pairs
+// Survivor-list capacity of the two-pass search: max(4096, n / 256) pairs
 // per query, at least 2^20 and at most 2^28.
 int64_t default_cap(int64_t n, int64_t q) {
-    int64_t per = std::max<int64_t>(2048, n / 512);
+    int64_t per = std::max<int64_t>(4096, n / 256);
     int64_t c = q * per;
     return std::min<int64_t>(std::max<int64_t>(c, (int64_t)1 << 20), (int64_t)1 << 28);
 }

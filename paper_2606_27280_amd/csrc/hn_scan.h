@@ -163,6 +163,7 @@ struct F32Tile : Shape16 {
     static constexpr int kFragRegs = kSlice;
     typedef Regs<kFragRegs> Frag;
     HN_SAME_Q_OPERAND
+    static constexpr bool kFused = true;  // the filter's flushes may rescore (psim)
     __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
         Acc acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -181,6 +182,7 @@ struct F32Tile32 : Shape32 {
     static constexpr int kFragRegs = kSlice;
     typedef Regs<kFragRegs> Frag;
     HN_SAME_Q_OPERAND
+    static constexpr bool kFused = true;  // the filter's flushes may rescore (psim)
     __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
         Acc acc = {};
 #pragma unroll
@@ -200,7 +202,7 @@ struct BF16Tile : Shape16 {
     static constexpr int kFragRegs = kSlice / 2;
     typedef Regs<kFragRegs> Frag;
     HN_SAME_Q_OPERAND
-    static constexpr bool kFused = true;  // the bf16 and int8 filters rescore in their flushes
+    static constexpr bool kFused = true;  // the filter's flushes may rescore (psim)
     __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
         Acc acc = {0.0f, 0.0f, 0.0f, 0.0f};
         if constexpr (kSlice == 4) {
@@ -230,7 +232,7 @@ struct BF16Tile32 : Shape32 {
     static constexpr int kFragRegs = kSlice / 2;
     typedef Regs<kFragRegs> Frag;
     HN_SAME_Q_OPERAND
-    static constexpr bool kFused = true;  // the bf16 and int8 filters rescore in their flushes
+    static constexpr bool kFused = true;  // the filter's flushes may rescore (psim)
     __device__ __forceinline__ static Acc mma(const Frag &x, const Frag &q) {
         Acc acc = {};
 #pragma unroll
@@ -305,7 +307,7 @@ struct I8Tile32 : Shape32 {
     static constexpr int kFragRegs = kSlice / 4;
     typedef Regs<kFragRegs> Frag;
     HN_SAME_Q_OPERAND
-    static constexpr bool kFused = true;  // the bf16 and int8 filters rescore in their flushes
+    static constexpr bool kFused = true;  // the filter's flushes may rescore (psim)
     // The filter compares these exact int32 sums with integer thresholds; the
     // other modes take them as float32 (exact: |sum| < 2^24).
     static constexpr bool kIntScores = true;

@@ -395,6 +395,7 @@ struct Overflow {
     int64_t *lower_idx = nullptr; // [q] its entry (-1: none)
     unsigned long long *count = nullptr;
     int64_t n = 0;                // host copy of *count after the batch
+    int64_t pairs = 0;            // the batch's survivor pairs, stored or not
 };
 
 __global__ __launch_bounds__(256) void collect_overflow(const int32_t *qflag, const QNorm *qn,
@@ -448,8 +449,9 @@ int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *o
     int rc = stage_seed(ix, queries, q, o, lower_in, lower_idx_in, cap, W, s, single);
     if (rc) return rc;
     ScanArgs A = filter_args(ix, W, q, W.pairs, cap);
-    // must match the tiles compiled with kFused (every bf16 and int8 tile)
-    const bool fused = W.precision == HN_PREC_BF16 || W.precision == HN_PREC_INT8;
+    // must match the tiles compiled with kFused (every float32, bf16 and int8
+    // tile)
+    const bool fused = W.precision != HN_PREC_FP8;
     if (single) {
         A.thr = W.win_scan;
         A.init_best = W.init_best;
@@ -461,11 +463,11 @@ int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *o
         hipLaunchKernelGGL(win_threshold, dim3(blocks_for(q, 4)), dim3(256), 0, s, W.part_val,
                            W.plan.n_chunks, (int32_t)W.plan.q_pad, q, W.win, W.thr, W.thr_ref);
     } else if (fused) {
-        // bf16 and int8: rescoring fused into the filter's flushes (the scan
-        // is bound by its epilogue and leaves HBM idle, so the row gathers of
-        // the survivors ride along).  Float32 keeps its pass purely on the
-        // matrix cores, fp8 (thousands of re-check rejects per query) keeps
-        // the separate re-check.
+        // float32, bf16 and int8: rescoring fused into the filter's flushes
+        // (the scan is bound by its matrix-core work or its epilogue and
+        // leaves HBM idle, so the row gathers of the survivors ride along,
+        // hidden behind the other waves' scanning); fp8 (thousands of
+        // re-check rejects per query) keeps the separate re-check.
         A.psim = W.psim;
         A.best_key = W.best_key;
         A.cnt = ((aux && aux->survivors) || stats) ? W.cnt : nullptr;
@@ -580,20 +582,22 @@ int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *o
         stats->overflow_queries = (int64_t)h[1];
     }
     if (ov) {
-        unsigned long long h = 0;
+        unsigned long long h = 0, pairs = 0;
         HN_HIP(hipMemcpyAsync(&h, ov->count, sizeof h, hipMemcpyDeviceToHost, s));
+        HN_HIP(hipMemcpyAsync(&pairs, W.counter, sizeof pairs, hipMemcpyDeviceToHost, s));
         HN_HIP(hipStreamSynchronize(s));
         ov->n = (int64_t)h;
+        ov->pairs = (int64_t)pairs;
     }
     return HN_OK;
 }
 
-// A batch whose survivor list may overflow (the single-pass forms and the
-// fp8 scan, whose slack keeps many more pairs), then its overflowing queries
-// again as a plain float32 filter pass seeded with the best candidate each
-// reached (exact: every entry that can beat that candidate survives the
-// filter, and the candidate is the seed).  Synchronises once to learn the
-// number of such queries.
+// A batch, then the queries whose survivors overflowed its pair list again as
+// a plain float32 filter pass seeded with the best candidate each reached
+// (exact: every entry that can beat that candidate survives the filter, and
+// the candidate is the seed), with a list as long as the first pass's pairs
+// (plain seed: the re-run's bound is at least as tight).  Synchronises once
+// to learn the number of such queries.
 int rerun_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *out_idx,
                 double *out_sim, const hn_search_opts &o, const hn_search_aux *aux,
                 hn_search_stats *stats, hipStream_t s) {
@@ -615,7 +619,11 @@ int rerun_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *ou
     hn_search_opts o2 = o;
     o2.seed = HN_SEED_PLAIN;
     o2.precision = HN_PREC_FP32;
-    o2.survivor_cap = 0;
+    // the plain seed's pairs bound the re-run's (its L is at least the
+    // seed's); a single pass's window pairs are no guide
+    o2.survivor_cap = std::min<int64_t>(
+        std::max<int64_t>(o.seed == HN_SEED_PLAIN ? ov.pairs : 0, default_cap(ix->n, ov.n)),
+        (int64_t)1 << 28);
     rc = search_batch(ix, sub_q, ov.n, sub_idx, sub_sim, o2, nullptr, nullptr, s, ov.lower,
                       ov.lower_idx, nullptr);
     if (rc) return rc;
@@ -658,8 +666,12 @@ extern "C" int hn_search_top1(const hn_index *ix, const float *queries, int64_t 
             a2.slack = aux->slack ? aux->slack + q0 : nullptr;
         }
         hn_search_stats st{0, 0};
-        if (o.seed == HN_SEED_PLAIN && o.precision != HN_PREC_FP8 &&
-            o.precision != HN_PREC_INT8)
+        // the plain seed on the float32 and bf16 scans never synchronises:
+        // queries whose survivors overflow its (generous) list are finished
+        // by the exhaustive pass; the other forms keep many more pairs per
+        // query and re-run their overflowing queries instead
+        if (o.seed == HN_SEED_PLAIN &&
+            (o.precision == HN_PREC_FP32 || o.precision == HN_PREC_BF16))
             rc = search_batch(ix, queries + q0 * kDim, nb, out_idx + q0, out_sim + q0, o,
                               aux ? &a2 : nullptr, stats ? &st : nullptr, s);
         else

@@ -131,6 +131,15 @@ def test_workload5_full_size_learned_seed(hn):
                                     L[sample] + 2.0 ** -40)
     s_plain = pa["survivors"].cpu().numpy()[sample]
     assert (hi <= s_plain).all() and (s_plain <= lo).all()
+    # the two bounds judged by the oracle: exact survivor sets S(q, L) at
+    # the plain seed's L and at the learned seed's L
+    Lq = la["seed_sim"].cpu().numpy()[sample]
+    Lq = np.where(np.isfinite(Lq), Lq, -np.inf)
+    at_plain, _ = oracle.survivor_counts(db, qs[sample], w.k, w.alpha, L[sample], L[sample])
+    at_learned, _ = oracle.survivor_counts(db, qs[sample], w.k, w.alpha, Lq, Lq)
+    assert (Lq <= plain[1].cpu().numpy()[sample]).all()  # a real entry's sim: admissible
+    say("workload5 oracle |S(q, L)| per query: plain L %.1f, learned L %.1f" % (
+        at_plain.mean(), at_learned.mean()))
     Ll = torch.nan_to_num(la["seed_sim"], neginf=float("nan"))
     say("workload5 pruned: plain seed %.4f%% (%.1f survivors/query, mean L %.3f), learned "
         "single pass %.4f%% (%.1f survivors/query, mean L %.3f)" % (

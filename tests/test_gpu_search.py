@@ -591,6 +591,31 @@ def test_workload2_full_size_sampled(hn):
     ix.close()
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp8", "int8"])
+def test_overflow_paths_exact(hn, precision):
+    """Two clusters over 30,000 entries: a query keeps thousands of
+    survivors, more than a list of 2,048 pairs per query holds, so most
+    queries overflow the first pass.  The fp32 and bf16 searches finish them
+    with the exhaustive float64 pass (no synchronisation); the fp8 and int8
+    searches search them again with a float32 filter pass seeded with their
+    best candidate and a list sized from the first pass's pair count; the
+    noalloc form takes the exhaustive pass.  All exact."""
+    k, alpha = 16, 1 / 8
+    db = hn_inputs.make_db(30000, k, alpha, 2, 6100)
+    qs = hn_inputs.make_queries(db, k, alpha, 40, 4, 6101)
+    ref = oracle.bnb_top1(db, qs, k, alpha)
+    ix = hn.Index(dev(db), k, alpha)
+    say("overflow paths %s: n=30000, 2 clusters" % precision)
+    cap = 2048 * len(qs)
+    idx, sim, st = ix.search(dev(qs), precision=precision, stats=True, survivor_cap=cap)
+    assert st["overflow_queries"] > len(qs) // 2
+    assert_exact(idx.cpu().numpy(), sim.cpu().numpy(), ref["idx"], ref["sim"], "overflow")
+    if precision in ("fp32", "bf16"):
+        ni, ns = ix.search_noalloc(dev(qs), precision=precision, survivor_cap=cap)
+        assert_exact(ni.cpu().numpy(), ns.cpu().numpy(), ref["idx"], ref["sim"], "noalloc")
+    ix.close()
+
+
 def test_fp8_overflow_rerun_exact(hn):
     """fp8 scans keep many more pairs; a list far too small sends the
     overflowing queries through a float32 filter pass seeded with the best
