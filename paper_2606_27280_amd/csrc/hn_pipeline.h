@@ -802,7 +802,13 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalArgs F) {
     if (F.aux.threshold) F.aux.threshold[o] = F.thr ? F.thr[i] : (float)NAN;
     if (F.aux.slack) F.aux.slack[o] = F.slack ? F.slack[i] : (double)NAN;
     if (F.n_flagged && F.qflag[i]) atomicAdd(F.n_flagged, 1ull);
-    if (F.ts_end) atomicMax(&F.ts_end[F.gdb[i]], (unsigned long long)wall_clock64());
+    if (F.ts_end) {
+        // the lanes of a wave write together: only the last lane of each
+        // database's run in the wave records the time
+        const DbRef &D = F.db[F.gdb[i]];
+        if (i - D.pad_base + 1 == D.q || (threadIdx.x & 63) == 63 || i + 1 == F.q)
+            atomicMax(&F.ts_end[F.gdb[i]], (unsigned long long)wall_clock64());
+    }
 }
 
 // ------------------------------------------------------------ exact top-k
