@@ -400,7 +400,7 @@ int hn_multi_search(hn_multi_plan *plan, const float *queries, int64_t *out_idx,
                     double *out_sim, int32_t use_graph, void *stream);
 
 /* Plan facts (host outputs, any may be NULL): total queries, scan work items
- * (per scan pass), scan launches per search. */
+ * (both scan passes together), scan launches per search. */
 int hn_multi_plan_info(const hn_multi_plan *plan, int64_t *total_queries, int64_t *work_items,
                        int32_t *scan_launches);
 

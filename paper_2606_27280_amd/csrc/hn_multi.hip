@@ -17,9 +17,16 @@
 namespace hn {
 namespace {
 
+// Shortest argmax-pass work item of a multi-database plan, in entry blocks
+// (measured on the 64-database set: 128 blocks took the pass from 0.77 to
+// 0.59 ms; the filter pass is faster with the usual shorter chunks).
+constexpr int kMultiArgmaxBlocks = 128;
+
 struct MultiGroup {
     int width = 0, cfg = 0;
-    int64_t item_off = 0;  // first item of the group in the item list
+    int64_t arg_off = 0;   // first argmax-pass item of the group in the item list
+    int arg_items = 0;
+    int64_t item_off = 0;  // first filter-pass item of the group in the item list
     int n_items = 0;
 };
 
@@ -140,10 +147,10 @@ int enqueue(hn_multi_plan *P, const float *queries, int64_t *out_idx, double *ou
     }
     for (int g = 0; g < ng; ++g) {
         const MultiGroup &G = P->groups[g];
-        if (G.n_items == 0) continue;
+        if (G.arg_items == 0) continue;
         ProfScope prof_(s, "multi_scan_argmax");
         if (launch_scan_multi(P->precision, kArgmax, G.width, G.cfg, P->scan_argmax,
-                              P->items + G.item_off, G.n_items, P->redo + G.item_off,
+                              P->items + G.arg_off, G.arg_items, P->redo + G.arg_off,
                               P->redo_counts + g, P->item_ctrs + (2 * g) * kXcds, s))
             return fail(HN_ERR_INVALID_ARG, "no multi-database scan for width %d", G.width);
     }
@@ -283,22 +290,33 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
     for (int d = 0; d < n_db; ++d)
         group_of[d] = (int)(std::lower_bound(widths.begin(), widths.end(), width[d]) - widths.begin());
 
-    // per-database plans and the padded query layout
-    std::vector<Plan> plan(n_db);
+    // per-database plans and the padded query layout.  The argmax pass has
+    // no survivors to stage, so its items can be long: at least
+    // kMultiArgmaxBlocks entry blocks (or the whole database), which keeps
+    // each item's fixed costs (claim, query tiles, partials) small against
+    // its scan when most databases hold few queries; the filter pass keeps
+    // the usual chunks, whose survivors fit the per-wave staging buffers.
+    std::vector<Plan> plan(n_db), aplan(n_db);
     std::vector<int64_t> pad_base(n_db), out_base(n_db), part_off(n_db), op_off(n_db);
     int64_t total_pad = 0, total_part = 0, total_op = 0, cap = 0;
     int64_t o_cum = 0;
     for (int d = 0; d < n_db; ++d) {
         const TileInfo ti = tile_info(o.precision, width[d]);
-        if (q_counts[d] > 0)
-            plan[d] = make_plan(ixs[d]->n, q_counts[d], P->groups[group_of[d]].cfg, o.chunk_blocks,
-                                ti.rows, ti.cols);
+        if (q_counts[d] > 0) {
+            const int cfg = P->groups[group_of[d]].cfg;
+            plan[d] = make_plan(ixs[d]->n, q_counts[d], cfg, o.chunk_blocks, ti.rows, ti.cols);
+            aplan[d] = o.chunk_blocks > 0
+                           ? plan[d]
+                           : make_plan(ixs[d]->n, q_counts[d], cfg,
+                                       std::max(plan[d].chunk_blocks, kMultiArgmaxBlocks),
+                                       ti.rows, ti.cols);
+        }
         pad_base[d] = total_pad;
         out_base[d] = o_cum;
         part_off[d] = total_part;
         op_off[d] = total_op;
         total_pad += plan[d].q_pad;
-        total_part += (int64_t)plan[d].n_chunks * plan[d].q_pad;
+        total_part += (int64_t)aplan[d].n_chunks * aplan[d].q_pad;
         total_op += plan[d].q_pad * width[d];
         o_cum += q_counts[d];
         if (q_counts[d] > 0) cap += default_cap(ixs[d]->n, q_counts[d]);
@@ -307,21 +325,25 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
     cap = std::max<int64_t>(cap, 1);
     P->total_pad = total_pad;
     P->cap = cap;
-    // item lists, group by group
+    // item lists, group by group: the argmax pass's, then the filter pass's
     std::vector<int2> items;
     for (size_t g = 0; g < P->groups.size(); ++g) {
         MultiGroup &G = P->groups[g];
-        G.item_off = (int64_t)items.size();
-        for (int d = 0; d < n_db; ++d) {
-            if (group_of[d] != (int)g) continue;
-            for (int it = 0; it < plan[d].n_items; ++it) items.push_back(make_int2(d, it));
+        for (int pass = 0; pass < 2; ++pass) {
+            const std::vector<Plan> &pl = pass == 0 ? aplan : plan;
+            const int64_t off = (int64_t)items.size();
+            for (int d = 0; d < n_db; ++d) {
+                if (group_of[d] != (int)g) continue;
+                for (int it = 0; it < pl[d].n_items; ++it) items.push_back(make_int2(d, it));
+            }
+            const int64_t cnt = (int64_t)items.size() - off;
+            if (cnt >= ((int64_t)1 << 31)) {
+                plan_destroy(P);
+                return fail(HN_ERR_UNSUPPORTED, "too many work items");
+            }
+            (pass == 0 ? G.arg_off : G.item_off) = off;
+            (pass == 0 ? G.arg_items : G.n_items) = (int)cnt;
         }
-        const int64_t cnt = (int64_t)items.size() - G.item_off;
-        if (cnt >= ((int64_t)1 << 31)) {
-            plan_destroy(P);
-            return fail(HN_ERR_UNSUPPORTED, "too many work items");
-        }
-        G.n_items = (int)cnt;
     }
     P->total_items = (int64_t)items.size();
 
@@ -397,7 +419,7 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
     std::vector<int64_t> o2p((size_t)std::max<int64_t>(total_q, 1), 0);
     for (int d = 0; d < n_db; ++d) {
         const hn_index *ix = ixs[d];
-        const Plan &p = plan[d];
+        const Plan &p = plan[d], &pa = aplan[d];
         const int g = group_of[d];
         const int w = width[d];
         void *opd = op + op_off[d] * esz;
@@ -408,19 +430,28 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
         A.qs = opd;
         A.q_stride = w;
         A.n = ix->n;
+        A.n_blocks = pa.n_blocks;
+        A.chunk_blocks = pa.chunk_blocks;
+        A.n_chunks = pa.n_chunks;
+        A.n_qb = pa.n_qb;
+        A.n_items = pa.n_items;
+        A.q_count = (int32_t)q_counts[d];
+        A.q_pad = (int32_t)pa.q_pad;
+        A.part_val = part_val + part_off[d];
+        A.part_idx = part_idx + part_off[d];
+        A.redo = P->redo + P->groups[g].arg_off;
+        A.redo_count = P->redo_counts + g;
+        A.q_base = (int32_t)pad_base[d];
+        sa[d] = A;
         A.n_blocks = p.n_blocks;
         A.chunk_blocks = p.chunk_blocks;
         A.n_chunks = p.n_chunks;
         A.n_qb = p.n_qb;
         A.n_items = p.n_items;
-        A.q_count = (int32_t)q_counts[d];
         A.q_pad = (int32_t)p.q_pad;
-        A.part_val = part_val + part_off[d];
-        A.part_idx = part_idx + part_off[d];
+        A.part_val = nullptr;
+        A.part_idx = nullptr;
         A.redo = P->redo + P->groups[g].item_off;
-        A.redo_count = P->redo_counts + g;
-        A.q_base = (int32_t)pad_base[d];
-        sa[d] = A;
         A.thr = P->thr + pad_base[d];
         A.pairs = P->pairs;
         A.counter = P->counter;
@@ -448,9 +479,9 @@ extern "C" int hn_multi_plan_create(const hn_index *const *ixs, int32_t n_db,
         memset(&S, 0, sizeof S);
         S.part_val = part_val + part_off[d];
         S.part_idx = part_idx + part_off[d];
-        S.n_chunks = p.n_chunks;
-        S.q_pad = (int32_t)p.q_pad;
-        S.part_ld = (int32_t)p.q_pad;
+        S.n_chunks = pa.n_chunks;
+        S.q_pad = (int32_t)pa.q_pad;
+        S.part_ld = (int32_t)pa.q_pad;
         S.shape = 32;
         S.group_size = 16 * kArgSpan;
         S.queries = P->q_buf + pad_base[d] * kDim;

@@ -695,10 +695,14 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
     };
     constexpr int kStep = PF * NS;  // blocks per group for this wave
     // The scheduling barriers keep each group's loads ahead of the other
-    // group's compute, so they have a whole compute phase to land.
+    // group's compute, so they have a whole compute phase to land.  A wave
+    // whose query tiles are all padding (a small batch in a large query
+    // block) skips the scan: its scores could never pass or be used, and the
+    // SIMD goes to the other waves.  The test is uniform in the wave.
     Frag xa[PF], xb[PF];
-    load_group(xa, blk0 + ws);
-    for (int base = blk0 + ws; base < blk1; base += 2 * kStep) {
+    const bool live = tile0 * C < A.q_count;
+    if (live) load_group(xa, blk0 + ws);
+    for (int base = blk0 + ws; live && base < blk1; base += 2 * kStep) {
         load_group(xb, base + kStep);
         __builtin_amdgcn_sched_barrier(0);
         compute_group(xa, base);
