@@ -960,6 +960,15 @@ def main():
         "forms_queries_per_s": forms,
     }
     res.update(out)
+    ctx = PAPER_TABLE3.get((w.k, w.alpha))
+    if ctx is not None and "speedup_vs_bruteforce" in res:
+        # the paper's own speed-up at this (K, alpha): a CPU search against
+        # a CPU brute force on another machine and data set
+        res["paper_context"] = {
+            "speedup_vs_bruteforce": ctx[0], "phase2_pct": ctx[1],
+            "where": "Table 3: N = 500,000 trevi descriptors, CPU (Core Ultra 7 256V) "
+                     "HN search against a CPU brute-force scan",
+            "note": "another machine, baseline and data set: context, not a target"}
     if seed_report is not None:
         res["seed_model"] = seed_report
         res["seed_forms"] = seed_forms
