@@ -805,6 +805,12 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
 template <class Tile, int NQ, int WQ, int MODE>
 __global__ __launch_bounds__(256) HN_SCAN_ATTR void scan_kernel(ScanArgs A) {
     HN_SCAN_SHARED(Tile, NQ, MODE)
+    // The single-pass window keeps a few percent of the entries, more than a
+    // wave's staging buffer holds for nearly every item: it flushes whenever
+    // the buffer fills (direct mode) instead of re-running the items that
+    // overflowed.  The two-pass filter's survivors are sparse: it flushes once
+    // per item and re-runs the rare overflowing item.
+    constexpr bool kDirect = MODE == kWindow;
     const int groups_per_xcd = (int)gridDim.x / kXcds;
     const int x = (int)(blockIdx.x % kXcds), w = (int)(blockIdx.x / kXcds);
     const int per = (A.n_items + kXcds - 1) / kXcds;
@@ -828,11 +834,11 @@ __global__ __launch_bounds__(256) HN_SCAN_ATTR void scan_kernel(ScanArgs A) {
             return it;
         };
         for (int item = claim(); item < hi; item = claim())
-            scan_item<Tile, NQ, WQ, MODE, false>(A, item, item, sh_val, sh_idx, sh_full, eb);
+            scan_item<Tile, NQ, WQ, MODE, kDirect>(A, item, item, sh_val, sh_idx, sh_full, eb);
         return;
     }
     for (int item = lo + w; item < hi; item += groups_per_xcd)
-        scan_item<Tile, NQ, WQ, MODE, false>(A, item, item, sh_val, sh_idx, sh_full, eb);
+        scan_item<Tile, NQ, WQ, MODE, kDirect>(A, item, item, sh_val, sh_idx, sh_full, eb);
 }
 
 // Re-runs the items whose survivor buffers overflowed, flushing as it goes.
