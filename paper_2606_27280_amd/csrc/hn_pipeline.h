@@ -604,10 +604,48 @@ __device__ __forceinline__ int64_t pair_count(const RescoreArgs &R) {
     return (int64_t)c < R.cap ? (int64_t)c : R.cap;
 }
 
+// The window re-filter (pair_val >= thr32[query]): after the single pass's
+// threshold refinement nearly every pair falls below it, so the kernel is
+// bound by reading the pairs.  Each thread takes kWinBatch pairs per step
+// with their loads in flight together, and only the kept pairs get a psim
+// (the tie kernel applies the same test before it reads one).
+constexpr int kWinBatch = 4;
+
+__device__ __forceinline__ void rescore_window_pairs(const RescoreArgs &R, int64_t m) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t p0 = (int64_t)blockIdx.x * 256 + threadIdx.x; p0 < m;
+         p0 += kWinBatch * stride) {
+        int2 pr[kWinBatch];
+        float pv[kWinBatch];
+#pragma unroll
+        for (int u = 0; u < kWinBatch; ++u) {
+            const int64_t p = p0 + u * stride;
+            pr[u] = p < m ? R.pairs[p] : make_int2(-1, -1);
+            pv[u] = p < m ? R.pair_val[p] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < kWinBatch; ++u) {
+            const int64_t p = p0 + u * stride;
+            const bool valid = pr[u].x >= 0;
+            if (valid && R.count) atomicAdd(&R.cnt[pr[u].x], 1);
+            if (!(valid && pv[u] >= R.thr32[pr[u].x])) continue;
+            const double s =
+                sim64(R.queries + (int64_t)pr[u].x * kDim, R.rows + (int64_t)pr[u].y * kDim);
+            const unsigned long long kk = key_of(s);
+            if (kk > R.best_key[pr[u].x]) atomicMax(&R.best_key[pr[u].x], kk);
+            R.psim[p] = s;
+        }
+    }
+}
+
 // MODE 0: plain; 1: float32 re-check against thr32 first; 2: window re-filter.
 template <int MODE>
 __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs R) {
     const int64_t m = pair_count(R);
+    if constexpr (MODE == 2) {
+        rescore_window_pairs(R, m);
+        return;
+    }
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < m;
          p += (int64_t)gridDim.x * 256) {
         const int2 pr = R.pairs[p];
@@ -657,9 +695,11 @@ __global__ __launch_bounds__(256) void tie_kernel(RescoreArgs R) {
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < m + R.q;
          p += (int64_t)gridDim.x * 256) {
         if (p < m) {
+            const int2 pr = R.pairs[p];
+            // window pairs below the re-filter threshold have no psim
+            if (R.pair_val && !(R.pair_val[p] >= R.thr32[pr.x])) continue;
             const double s = R.psim[p];
             if (s == -INFINITY) continue;
-            const int2 pr = R.pairs[p];
             if (key_of(s) == R.best_key[pr.x]) atomicMin(&R.best_idx[pr.x], pr.y);
         } else if (R.seed_idx) {
             const int64_t qi = p - m;
@@ -1056,13 +1096,59 @@ __global__ __launch_bounds__(256) void prefix_max(const float *part_val, int32_t
 // Single-pass re-filter threshold: max(T_q, m - w_q) with m the final scan
 // maximum over all chunks (which includes the starting value T_q + w_q).
 // Same launch shape as bf_threshold.
+// Also records m (win_max) and clears the entry of the pair that scored it
+// (win_arg, INT_MAX: none found yet).
 __global__ __launch_bounds__(256) void win_threshold(const float *part_val, int32_t n_chunks,
                                                      int32_t q_pad, int64_t q, const double *win,
-                                                     const float *thr, float *out) {
+                                                     const float *thr, float *out,
+                                                     float *win_max, int32_t *win_arg) {
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= q) return;
     const float m = chunk_max(part_val, n_chunks, q_pad, i, threadIdx.x & 63);
-    if ((threadIdx.x & 63) == 0) out[i] = fmaxf(thr[i], __double2float_rd((double)m - win[i]));
+    if ((threadIdx.x & 63) == 0) {
+        out[i] = fmaxf(thr[i], __double2float_rd((double)m - win[i]));
+        win_max[i] = m;
+        win_arg[i] = INT_MAX;
+    }
+}
+
+// The entry of the final scan maximum: the pair whose score equals m (the
+// entry that raised the running maximum to m was inside its own window, so
+// it was stored).  Several such pairs: the smallest entry.
+__global__ __launch_bounds__(256) void win_argmax(const int2 *__restrict__ pairs,
+                                                  const float *__restrict__ pair_val,
+                                                  const unsigned long long *counter, int64_t cap,
+                                                  const float *__restrict__ win_max,
+                                                  int32_t *win_arg) {
+    const unsigned long long c = *counter;
+    const int64_t m = (int64_t)c < cap ? (int64_t)c : cap;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < m;
+         p += (int64_t)gridDim.x * 256) {
+        const float v = pair_val[p];
+        const int2 pr = pairs[p];
+        if (v == win_max[pr.x]) atomicMin(&win_arg[pr.x], pr.y);
+    }
+}
+
+// Algorithm 1's seed taken from the single pass itself: the entry of the
+// final scan maximum is the best major-dot entry, so its canonical sim L' is
+// an admissible lower bound, and the re-filter threshold rises to
+// round_down((L' - beta - eps_q) / unit), the plain seed's threshold at L'
+// (never above m, so that entry's own pair is always rescored).  One thread
+// per query; queries without a stored maximum keep the window threshold.
+__global__ __launch_bounds__(256) void win_refine(SeedArgs S, const float *__restrict__ win_max,
+                                                  const int32_t *__restrict__ win_arg,
+                                                  float *thr_ref) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= S.q) return;
+    const int32_t j = win_arg[i];
+    const QNorm qn = S.qn[i];
+    if (j == INT_MAX || qn.bad) return;
+    const double L = sim64(S.queries + i * kDim, S.rows + (int64_t)j * kDim);
+    const double unit =
+        S.scaled ? 1.0 / ((double)(S.scaled == 1 ? qn.sc8 : qn.sci) * S.scale_x) : 1.0;
+    const float t = round_down_f32((L - S.beta - S.slack[i]) * unit);
+    thr_ref[i] = fmaxf(thr_ref[i], fminf(t, win_max[i]));
 }
 
 __global__ void fill_lower(double *lower, int64_t *idx, int64_t q) {

@@ -45,8 +45,11 @@ struct Work {
     // single-pass forms
     double *win = nullptr;
     float *win_scan = nullptr, *init_best = nullptr, *thr_ref = nullptr, *pair_val = nullptr;
+    float *win_max = nullptr;
+    int32_t *win_arg = nullptr;
     double *lower = nullptr;
     int64_t *lower_idx = nullptr;
+    SeedArgs seed_args;  // as the seed kernel ran (the single pass's refinement reuses it)
 };
 
 const void *operands_of(const Work &W) {
@@ -171,6 +174,8 @@ size_t stage_bytes(const hn_index *ix, int64_t q, const Work &W, bool window,
         add(q, 4);
         add(q, 8);
         add(q, 8);
+        add(q, 4);
+        add(q, 4);
     }
     // pairs (int2), their float64 sims and, with the window, their scores;
     // plus the rounding of each of those arrays to 256 bytes
@@ -233,6 +238,8 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
         W.thr_ref = ar->take<float>(q);
         W.lower = ar->take<double>(q);
         W.lower_idx = ar->take<int64_t>(q);
+        W.win_max = ar->take<float>(q);
+        W.win_arg = ar->take<int32_t>(q);
     }
     W.pairs = ar->take<int2>(cap);
     W.psim = ar->take<double>(cap);
@@ -323,6 +330,7 @@ int stage_seed(const hn_index *ix, const float *queries, int64_t q, const hn_sea
         ProfScope prof_(s, "seed");
         hipLaunchKernelGGL(seed_kernel, dim3(blocks_for(qp, 4)), dim3(256), 0, s, S);
     }
+    W.seed_args = S;
     HN_HIP(hipGetLastError());
     return HN_OK;
 }
@@ -461,7 +469,14 @@ int search_batch(const hn_index *ix, const float *queries, int64_t q, int64_t *o
         if (rc) return rc;
         ProfScope prof_(s, "win_threshold");
         hipLaunchKernelGGL(win_threshold, dim3(blocks_for(q, 4)), dim3(256), 0, s, W.part_val,
-                           W.plan.n_chunks, (int32_t)W.plan.q_pad, q, W.win, W.thr, W.thr_ref);
+                           W.plan.n_chunks, (int32_t)W.plan.q_pad, q, W.win, W.thr, W.thr_ref,
+                           W.win_max, W.win_arg);
+        // rescore the entry of each query's final maximum and raise the
+        // re-filter threshold to the plain seed's threshold at its sim
+        hipLaunchKernelGGL(win_argmax, dim3(2048), dim3(256), 0, s, W.pairs, W.pair_val,
+                           W.counter, cap, W.win_max, W.win_arg);
+        hipLaunchKernelGGL(win_refine, dim3(blocks_for(q)), dim3(256), 0, s, W.seed_args,
+                           W.win_max, W.win_arg, W.thr_ref);
     } else if (fused) {
         // float32, bf16 and int8: rescoring fused into the filter's flushes
         // (the scan is bound by its matrix-core work or its epilogue and
