@@ -81,6 +81,7 @@ struct Shape16 {
     static constexpr int kRows = 16, kCols = 16, kGroups = 4, kAcc = 4;
     static constexpr bool kIntScores = false;  // exact integer sums (mma_i)
     static constexpr bool kFused = false;      // filter flush may rescore (psim)
+    static constexpr bool kDenseFilter = false;  // filter flushes as it goes (direct)
     typedef v4f Acc;
     __device__ __forceinline__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
@@ -89,6 +90,7 @@ struct Shape32 {
     static constexpr int kRows = 32, kCols = 32, kGroups = 2, kAcc = 16;
     static constexpr bool kIntScores = false;  // exact integer sums (mma_i)
     static constexpr bool kFused = false;      // filter flush may rescore (psim)
+    static constexpr bool kDenseFilter = false;  // filter flushes as it goes (direct)
     typedef v16f Acc;
     __device__ __forceinline__ static int out_row(int lane, int v) {
         return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -256,6 +258,10 @@ struct BF16Tile32 : Shape32 {
 // The query operand is decoded once, at load.
 template <int W>
 struct FP8Tile32 : Shape32 {
+    // the fp8 slack keeps many more pairs than the other precisions (for
+    // K = 8, thousands per query): most items would overflow their staging
+    // buffers and be re-run, so the filter flushes whenever a buffer fills
+    static constexpr bool kDenseFilter = true;
     typedef uint8_t Elem;
     static constexpr int kSlice = W / 2;           // codes per lane group
     static constexpr int kFragRegs = kSlice / 4;   // entry operand: 4 codes per register
@@ -809,8 +815,9 @@ __global__ __launch_bounds__(256) HN_SCAN_ATTR void scan_kernel(ScanArgs A) {
     // wave's staging buffer holds for nearly every item: it flushes whenever
     // the buffer fills (direct mode) instead of re-running the items that
     // overflowed.  The two-pass filter's survivors are sparse: it flushes once
-    // per item and re-runs the rare overflowing item.
-    constexpr bool kDirect = MODE == kWindow;
+    // per item and re-runs the rare overflowing item, except with a tile
+    // whose slack keeps dense survivors (kDenseFilter).
+    constexpr bool kDirect = MODE == kWindow || (MODE == kFilter && Tile::kDenseFilter);
     const int groups_per_xcd = (int)gridDim.x / kXcds;
     const int x = (int)(blockIdx.x % kXcds), w = (int)(blockIdx.x / kXcds);
     const int per = (A.n_items + kXcds - 1) / kXcds;
@@ -866,12 +873,13 @@ __global__ __launch_bounds__(256) void scan_multi_kernel(const ScanArgs *__restr
     const int x = (int)(blockIdx.x % kXcds), w = (int)(blockIdx.x / kXcds);
     const int per = (n_items + kXcds - 1) / kXcds;
     const int lo = x * per, hi = min(n_items, lo + per);
+    constexpr bool kDirect = MODE == kFilter && Tile::kDenseFilter;  // as in scan_kernel
     auto run = [&](int item) {
         const int2 it = items[item];
         const int d = __builtin_amdgcn_readfirstlane(it.x);
         const int local = __builtin_amdgcn_readfirstlane(it.y);
         const ScanArgs A = dbs[d];
-        scan_item<Tile, NQ, WQ, MODE, false>(A, local, item, sh_val, sh_idx, sh_full, eb);
+        scan_item<Tile, NQ, WQ, MODE, kDirect>(A, local, item, sh_val, sh_idx, sh_full, eb);
     };
     if (item_ctr) {
         // device work queue: items of databases of very different sizes and
