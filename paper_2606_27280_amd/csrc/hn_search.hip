@@ -823,6 +823,22 @@ extern "C" int hn_search_topk(const hn_index *ix, const float *queries, int64_t 
         rc = stage_seed(ix, queries, q, o, nullptr, nullptr, cap, W, s, false, topk);
         if (rc) return rc;
         ScanArgs A = filter_args(ix, W, q, W.pairs, cap);
+        // float32, bf16 and int8: the filter's flushes store each pair's
+        // canonical sim and count it, as the rescoring kernel would
+        const bool fused = W.precision != HN_PREC_FP8;
+        if (fused) {
+            A.psim = W.psim;
+            A.best_key = W.best_key;
+            A.cnt = W.cnt;
+            A.rs_queries = queries;
+            A.rs_rows = ix->rows;
+            if (W.precision != HN_PREC_FP32) {
+                A.rs_major32 = ix->major32;
+                A.rs_thr32 = W.thr32;
+                A.rs_kp = ix->kp;
+                A.rs_k = ix->k;
+            }
+        }
         rc = launch_scan<kFilter>(W.precision, W.width, W.cfg, W.plan, A, s);
         if (rc) return rc;
         RescoreArgs R;
@@ -842,12 +858,9 @@ extern "C" int hn_search_topk(const hn_index *ix, const float *queries, int64_t 
         R.cnt = W.cnt;
         R.q = q;
         R.count = 1;
-        {
+        if (!fused) {
             ProfScope prof_(s, "topk_rescore");
-            if (W.precision == HN_PREC_FP32)
-                hipLaunchKernelGGL(rescore_kernel<0>, dim3(2048), dim3(256), 0, s, R);
-            else
-                hipLaunchKernelGGL(rescore_kernel<1>, dim3(2048), dim3(256), 0, s, R);
+            hipLaunchKernelGGL(rescore_kernel<1>, dim3(2048), dim3(256), 0, s, R);
         }
         HN_HIP(hipMemcpyAsync(&total, W.counter, sizeof total, hipMemcpyDeviceToHost, s));
         HN_HIP(hipStreamSynchronize(s));
