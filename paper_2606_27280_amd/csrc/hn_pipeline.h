@@ -1133,9 +1133,11 @@ __global__ __launch_bounds__(256) void win_argmax(const int2 *__restrict__ pairs
 // Algorithm 1's seed taken from the single pass itself: the entry of the
 // final scan maximum is the best major-dot entry, so its canonical sim L' is
 // an admissible lower bound, and the re-filter threshold rises to
-// round_down((L' - beta - eps_q) / unit), the plain seed's threshold at L'
-// (never above m, so that entry's own pair is always rescored).  One thread
-// per query; queries without a stored maximum keep the window threshold.
+// round_down((L' - beta - eps_q) * u), the plain seed's threshold at L' in
+// scan units (u = 1 / (s_q s_x) for the scaled fp8 and int8 scans, else 1),
+// but never above m, so that entry's own pair is always rescored.  One
+// thread per query; queries without a stored maximum keep the window
+// threshold.
 __global__ __launch_bounds__(256) void win_refine(SeedArgs S, const float *__restrict__ win_max,
                                                   const int32_t *__restrict__ win_arg,
                                                   float *thr_ref) {

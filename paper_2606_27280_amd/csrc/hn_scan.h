@@ -837,10 +837,10 @@ __global__ __launch_bounds__(256) HN_SCAN_ATTR void scan_kernel(ScanArgs A) {
             // each, and flushes whenever its staging buffer fills.  No wave
             // waits at a barrier for another one's survivors.  The counters
             // count sub-block items, kWaves per item, in the same per-XCD
-            // ranges as the items.  (Measured on the 1M-entry benchmark:
-            // +3% float32 and bf16; the int8 filter, whose integer emission
-            // does not take the inline flushes well, ran at half speed and
-            // keeps work-group items.)
+            // ranges as the items.  (Measured with 10,000 queries on 2^20
+            // entries: +3% float32 and bf16; the int8 filter, whose integer
+            // emission does not take the inline flushes well, ran at half
+            // speed and keeps work-group items.)
             const int nw = A.n_items * kWaves;
             const int wper = (nw + kXcds - 1) / kXcds;
             const int wlo = x * wper, whi = min(nw, wlo + wper);
