@@ -238,7 +238,7 @@ def test_single_pass_forms_exact(hn):
     ref = oracle.bnb_top1(db, qs, w.k, w.alpha)
     surv = {}
     for seed in ("learned", "window"):
-        for prec in ("fp32", "bf16", "fp8"):
+        for prec in ("fp32", "bf16", "fp8", "int8"):
             say("single pass seed=%s precision=%s" % (seed, prec))
             idx, sim, aux, st = ix.search(dev(qs), precision=prec, seed=seed, aux=True,
                                           stats=True)
@@ -254,8 +254,32 @@ def test_single_pass_forms_exact(hn):
                 for qi in range(0, len(qs), 9):
                     assert ss[qi] == oracle.sim(qs[qi], db[si[qi]])
     # the seed only raises the window's floor: never more survivors
-    for prec in ("fp32", "bf16", "fp8"):
+    for prec in ("fp32", "bf16", "fp8", "int8"):
         assert (surv[("learned", prec)] <= surv[("window", prec)]).all()
+    ix.close()
+
+
+@pytest.mark.parametrize("frac", [0.5, 0.0])
+def test_single_pass_soft_mode_returns_real_entries(hn, frac):
+    """The window-only single pass with beta < alpha (Section 7's soft mode):
+    the result is a real entry with its canonical sim, never better than the
+    exact best, and its re-filter threshold (raised to the bound at the sim
+    of the entry that scored the final maximum, capped at that maximum)
+    leaves the pass's own maximum rescored: every query gets an entry."""
+    w = hn_inputs.workload(1)
+    db = w.db()
+    qs = w.queries(db)[:96]
+    ix = hn.Index(dev(db), w.k, w.alpha)
+    ref = oracle.bnb_top1(db, qs, w.k, w.alpha)
+    beta = frac * w.alpha
+    for prec in ("fp32", "bf16"):
+        say("window single pass, soft mode beta=%g, %s" % (beta, prec))
+        idx, sim = ix.search(dev(qs), precision=prec, seed="window", beta=beta)
+        idx, sim = idx.cpu().numpy(), sim.cpu().numpy()
+        assert (idx >= 0).all() and (idx < len(db)).all()
+        assert (sim <= ref["sim"]).all()
+        for qi in range(len(qs)):
+            assert sim[qi] == oracle.sim(qs[qi], db[idx[qi]])
     ix.close()
 
 
