@@ -95,9 +95,11 @@ __device__ __forceinline__ double sim_of_key(unsigned long long k) {
 }
 
 // Canonical float64 sim: ascending j, each float32 product exact in float64.
+// kUnroll float4 groups of both rows load together (8: one 128-byte line).
+template <int kUnroll = 4>
 __device__ __forceinline__ double sim64(const float *__restrict__ q, const float *__restrict__ x) {
     double acc = 0.0;
-#pragma unroll 4
+#pragma unroll kUnroll
     for (int j = 0; j < kDim; j += 4) {
         float4 a = *reinterpret_cast<const float4 *>(q + j);
         float4 b = *reinterpret_cast<const float4 *>(x + j);

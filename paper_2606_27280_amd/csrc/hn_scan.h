@@ -408,27 +408,44 @@ __device__ __forceinline__ void flush_pairs(const ScanArgs &A, EmitBuf &B) {
             if (WithVal) A.pair_val[pos] = B.vals[i];
             if (Fused && !WithVal && A.psim) {
                 const float *qv = A.rs_queries + (int64_t)pr.x * kDim;
+                // the key and the threshold load with the re-check's row
+                // prefix, and the prefix loads go out together: the flush
+                // waits on as few dependent loads as possible
+                const unsigned long long bk = A.best_key[pr.x];
                 bool keep = true;
                 if (A.rs_major32) {
+                    const float thr = A.rs_thr32[pr.x];
                     const float *xm = A.rs_major32 + (int64_t)pr.y * A.rs_kp;
                     float sm = 0.0f;
-                    for (int j = 0; j < A.rs_k; j += 4) {
-                        const float4 x4 = *reinterpret_cast<const float4 *>(xm + j);
-                        const float4 q4 = *reinterpret_cast<const float4 *>(qv + j);
-                        sm = fmaf(q4.x, x4.x, sm);
-                        sm = fmaf(q4.y, x4.y, sm);
-                        sm = fmaf(q4.z, x4.z, sm);
-                        sm = fmaf(q4.w, x4.w, sm);
+                    for (int j0 = 0; j0 < A.rs_k; j0 += 16) {
+                        float4 x4[4], q4[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const bool ok = j0 + 4 * u < A.rs_k;
+                            x4[u] = ok ? *reinterpret_cast<const float4 *>(xm + j0 + 4 * u)
+                                       : make_float4(0.f, 0.f, 0.f, 0.f);
+                            q4[u] = ok ? *reinterpret_cast<const float4 *>(qv + j0 + 4 * u)
+                                       : make_float4(0.f, 0.f, 0.f, 0.f);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            if (j0 + 4 * u < A.rs_k) {
+                                sm = fmaf(q4[u].x, x4[u].x, sm);
+                                sm = fmaf(q4[u].y, x4[u].y, sm);
+                                sm = fmaf(q4[u].z, x4[u].z, sm);
+                                sm = fmaf(q4[u].w, x4[u].w, sm);
+                            }
+                        }
                     }
-                    keep = sm >= A.rs_thr32[pr.x];
+                    keep = sm >= thr;
                 }
                 double sv = -INFINITY;
                 if (keep) {
-                    sv = sim64(qv, A.rs_rows + (int64_t)pr.y * kDim);
+                    sv = sim64<8>(qv, A.rs_rows + (int64_t)pr.y * kDim);
                     // best_key starts at the seed's key and only grows: most
                     // survivors are below it and need no atomic
                     const unsigned long long kk = key_of(sv);
-                    if (kk > A.best_key[pr.x]) atomicMax(&A.best_key[pr.x], kk);
+                    if (kk > bk) atomicMax(&A.best_key[pr.x], kk);
                 }
                 A.psim[pos] = sv;
                 if (A.cnt) atomicAdd(&A.cnt[pr.x], 1);
