@@ -368,6 +368,23 @@ __device__ __forceinline__ float acc_max_from(float m, const Acc &a) {
     return m;
 }
 
+// Maximum of N slots and the maxima of its groups of 4 slots (the ballot
+// groups of emit_pairs), each from -inf as above: two max3 per group and two
+// more to combine four groups.
+template <class Acc, int N>
+__device__ __forceinline__ float acc_group_max(const Acc &a, float (&gm)[(N + 3) / 4]) {
+    float m = -INFINITY;
+#pragma unroll
+    for (int g = 0; g < (N + 3) / 4; ++g) {
+        float x = -INFINITY;
+#pragma unroll
+        for (int v = 4 * g; v < 4 * g + 4 && v < N; ++v) x = fmaxf(x, a[v]);
+        gm[g] = x;
+        m = fmaxf(m, x);
+    }
+    return m;
+}
+
 // Argmax spans: the argmax mode reduces the scores of kArgSpan consecutive
 // blocks into one running maximum per lane before comparing it with the
 // best so far, so a winning lane group is (span, g): kArgSpan x the group's
@@ -509,10 +526,11 @@ __device__ __forceinline__ void flush_pairs(const ScanArgs &A, EmitBuf &B) {
 // mask is the ballot itself.
 template <class Tile, bool WithVal, bool Direct, bool Batch, class AccT, class T>
 __device__ __forceinline__ void emit_pairs(const ScanArgs &A, EmitBuf &B, const AccT &a, T t,
-                                           int q, int eblk) {
+                                           int q, int eblk, unsigned groups = ~0u) {
     const int lane = (int)__lane_id();
 #pragma unroll
     for (int v0 = 0; v0 < Tile::kAcc; v0 += 4) {
+        if (!((groups >> (v0 / 4)) & 1u)) continue;  // wave-uniform: no lane's group passes
         bool pv[4];
         unsigned long long mv[4];
         int c[4];
@@ -710,7 +728,14 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
                         if (eblk + Tile::out_row(lane, v) >= A.n) acc[t][v] = __builtin_nanf("");
             }
             float mx[NQ];
-            if constexpr (MODE != kArgmax) {
+            // the filter keeps the maxima of the emission's groups of 4 slots:
+            // a tile with a survivor then ballots only the groups that hold one
+            constexpr int NG = (NA + 3) / 4;
+            float gmx[NQ][NG];
+            if constexpr (MODE == kFilter) {
+#pragma unroll
+                for (int t = 0; t < NQ; ++t) mx[t] = acc_group_max<Acc, NA>(acc[t], gmx[t]);
+            } else if constexpr (MODE != kArgmax) {
                 // from -inf: the tree is max3 operations only (no separate
                 // quieting of the first scores)
 #pragma unroll
@@ -730,10 +755,15 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
                 for (int t = 0; t < NQ; ++t) any = any || (mx[t] >= thr[t]);
                 if (__ballot(any)) {
 #pragma unroll
-                    for (int t = 0; t < NQ; ++t)
-                        if (__ballot(mx[t] >= thr[t]))
-                            emit_pairs<Tile, false, Direct, Batch>(A, eb, acc[t], thr[t], qid[t],
-                                                            eblk);
+                    for (int t = 0; t < NQ; ++t) {
+                        if (!__ballot(mx[t] >= thr[t])) continue;
+                        unsigned groups = 0;
+#pragma unroll
+                        for (int g = 0; g < NG; ++g)
+                            if (__ballot(gmx[t][g] >= thr[t])) groups |= 1u << g;
+                        emit_pairs<Tile, false, Direct, Batch>(A, eb, acc[t], thr[t], qid[t], eblk,
+                                                               groups);
+                    }
                 }
             } else if constexpr (MODE == kWindow) {
                 float lim[NQ];
