@@ -368,21 +368,24 @@ __device__ __forceinline__ float acc_max_from(float m, const Acc &a) {
     return m;
 }
 
-// Maximum of N slots and the maxima of its groups of 4 slots (the ballot
-// groups of emit_pairs), each from -inf as above: two max3 per group and two
-// more to combine four groups.
-template <class Acc, int N>
-__device__ __forceinline__ float acc_group_max(const Acc &a, float (&gm)[(N + 3) / 4]) {
-    float m = -INFINITY;
+// The emission's groups of 4 slots (bit g: slots 4g..4g+3) in which some
+// lane holds a score >= t: computed only on the rare tiles with a survivor,
+// from each group's maximum (two max operations and one ballot per group),
+// so that emit_pairs ballots and counts the slots of those groups alone.
+// (fmaxf: the NaN scores of rows past the end never hide a passing one.)
+__device__ __forceinline__ float slot_max(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ int slot_max(int a, int b) { return max(a, b); }
+template <int N, class AccT, class T>
+__device__ __forceinline__ unsigned group_mask(const AccT &a, T t) {
+    unsigned groups = 0;
 #pragma unroll
     for (int g = 0; g < (N + 3) / 4; ++g) {
-        float x = -INFINITY;
+        T x = a[4 * g];
 #pragma unroll
-        for (int v = 4 * g; v < 4 * g + 4 && v < N; ++v) x = fmaxf(x, a[v]);
-        gm[g] = x;
-        m = fmaxf(m, x);
+        for (int v = 4 * g + 1; v < 4 * g + 4 && v < N; ++v) x = slot_max(x, a[v]);
+        if (__ballot(x >= t)) groups |= 1u << g;
     }
-    return m;
+    return groups;
 }
 
 // Argmax spans: the argmax mode reduces the scores of kArgSpan consecutive
@@ -712,7 +715,8 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
 #pragma unroll
                     for (int t = 0; t < NQ; ++t)
                         if (__ballot(mi[t] >= thri[t]))
-                            emit_pairs<Tile, false, Direct, Batch>(A, eb, ai[t], thri[t], qid[t], eblk);
+                            emit_pairs<Tile, false, Direct, Batch>(A, eb, ai[t], thri[t], qid[t], eblk,
+                                                                   group_mask<NA>(ai[t], thri[t]));
                 }
                 continue;
             }
@@ -728,14 +732,7 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
                         if (eblk + Tile::out_row(lane, v) >= A.n) acc[t][v] = __builtin_nanf("");
             }
             float mx[NQ];
-            // the filter keeps the maxima of the emission's groups of 4 slots:
-            // a tile with a survivor then ballots only the groups that hold one
-            constexpr int NG = (NA + 3) / 4;
-            float gmx[NQ][NG];
-            if constexpr (MODE == kFilter) {
-#pragma unroll
-                for (int t = 0; t < NQ; ++t) mx[t] = acc_group_max<Acc, NA>(acc[t], gmx[t]);
-            } else if constexpr (MODE != kArgmax) {
+            if constexpr (MODE != kArgmax) {
                 // from -inf: the tree is max3 operations only (no separate
                 // quieting of the first scores)
 #pragma unroll
@@ -757,12 +754,8 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
 #pragma unroll
                     for (int t = 0; t < NQ; ++t) {
                         if (!__ballot(mx[t] >= thr[t])) continue;
-                        unsigned groups = 0;
-#pragma unroll
-                        for (int g = 0; g < NG; ++g)
-                            if (__ballot(gmx[t][g] >= thr[t])) groups |= 1u << g;
                         emit_pairs<Tile, false, Direct, Batch>(A, eb, acc[t], thr[t], qid[t], eblk,
-                                                               groups);
+                                                               group_mask<NA>(acc[t], thr[t]));
                     }
                 }
             } else if constexpr (MODE == kWindow) {
