@@ -663,18 +663,33 @@ __global__ __launch_bounds__(256) void rescore_kernel(RescoreArgs R) {
         bool keep = true;
         if (MODE == 1) {
             // the float32 prefix stream is zero padded to kp (a multiple of
-            // 4) and the query row holds 128 values: whole float4 groups
+            // 4) and the query row holds 128 values: whole float4 groups, the
+            // threshold and four groups of both rows in flight together
+            // (fp8 re-check 0.494 to 0.477 ms on 5.3 M pairs)
+            const float thr = R.thr32[pr.x];
             const float *xm = major32 + (int64_t)pr.y * kp;
             float s = 0.0f;
-            for (int j = 0; j < k; j += 4) {
-                const float4 x4 = *reinterpret_cast<const float4 *>(xm + j);
-                const float4 q4 = *reinterpret_cast<const float4 *>(qv + j);
-                s = fmaf(q4.x, x4.x, s);
-                s = fmaf(q4.y, x4.y, s);
-                s = fmaf(q4.z, x4.z, s);
-                s = fmaf(q4.w, x4.w, s);
+            for (int j0 = 0; j0 < k; j0 += 16) {
+                float4 x4[4], q4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool ok = j0 + 4 * u < k;
+                    x4[u] = ok ? *reinterpret_cast<const float4 *>(xm + j0 + 4 * u)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+                    q4[u] = ok ? *reinterpret_cast<const float4 *>(qv + j0 + 4 * u)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (j0 + 4 * u < k) {
+                        s = fmaf(q4[u].x, x4[u].x, s);
+                        s = fmaf(q4[u].y, x4[u].y, s);
+                        s = fmaf(q4[u].z, x4[u].z, s);
+                        s = fmaf(q4[u].w, x4[u].w, s);
+                    }
+                }
             }
-            keep = s >= R.thr32[pr.x];
+            keep = s >= thr;
         } else if (MODE == 2) {
             keep = R.pair_val[p] >= R.thr32[pr.x];
         }
