@@ -404,6 +404,11 @@ constexpr int kArgSpan = 4;
 #define HN_EMIT_CAP 1024
 #endif
 constexpr int kEmitCap = HN_EMIT_CAP;  // pairs per wave buffer (>= 64 lanes x 4 slots)
+// Wave-level filter items carry fewer than this many pairs to the wave's
+// next item instead of flushing them (float32 filter -1% on 10,000 queries
+// over 2^20 entries, where a wave's item holds about 50 pairs; carrying up
+// to a full buffer made every wave end on a long flush, 25% slower).
+constexpr int kCarryPairs = 128;
 static_assert(kEmitCap >= 256, "a flush must always fit four ballots of 64 lanes");
 
 struct EmitBuf {
@@ -583,7 +588,7 @@ __device__ __forceinline__ void lex_merge(float &v, int &i, float ov, int oi) {
 // sub_block >= 0: this wave alone scans that query sub-block of the item
 // (wave-level items, WQ = kWaves); else the wave's place in the work-group
 // decides.
-template <class Tile, int NQ, int WQ, int MODE, bool Direct, bool Batch = true>
+template <class Tile, int NQ, int WQ, int MODE, bool Direct, bool Batch = true, bool Carry = false>
 __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, const int redo_id,
                                           float (*sh_val)[NQ * Tile::kCols],
                                           int (*sh_idx)[NQ * Tile::kCols], int *sh_full,
@@ -811,7 +816,11 @@ __device__ __forceinline__ void scan_item(const ScanArgs &A, const int item, con
 
     if constexpr (MODE == kFilter || MODE == kWindow) {
         if constexpr (Direct) {
-            flush_pairs<MODE == kWindow, Tile::kFused, Batch>(A, eb);
+            // a wave that runs item after item (Carry) keeps fewer than
+            // kCarryPairs pairs for its next item's flush, so that a flush
+            // fills its lanes; it flushes the rest after its last item
+            if (!Carry || eb.count >= kCarryPairs)
+                flush_pairs<MODE == kWindow, Tile::kFused, Batch>(A, eb);
         } else {
             // flush only if no wave of the item overflowed; else re-run it.
             // The decision is made uniform explicitly: a branch the compiler
@@ -916,8 +925,10 @@ __global__ __launch_bounds__(256) HN_SCAN_ATTR void scan_kernel(ScanArgs A) {
             // Wave-level items: with one query sub-block per wave the four
             // waves of a work-group share nothing but the entry chunk, so
             // each wave claims (item, sub-block) pairs alone, one atomic
-            // each, and flushes whenever its staging buffer fills.  No wave
-            // waits at a barrier for another one's survivors.  The counters
+            // each, and flushes whenever its staging buffer fills (and after
+            // an item that leaves kCarryPairs pairs or more, the rest after
+            // its last item).  No wave waits at a barrier for another one's
+            // survivors.  The counters
             // count sub-block items, kWaves per item, in the same per-XCD
             // ranges as the items.  (Measured with 10,000 queries on 2^20
             // entries: +3% float32 and bf16; the int8 filter, whose integer
@@ -932,8 +943,9 @@ __global__ __launch_bounds__(256) HN_SCAN_ATTR void scan_kernel(ScanArgs A) {
                 return wlo + (int)__builtin_amdgcn_readfirstlane(v);
             };
             for (int wi = claim_sub(); wi < whi; wi = claim_sub())
-                scan_item<Tile, NQ, WQ, MODE, true>(A, wi / kWaves, wi / kWaves, sh_val, sh_idx,
-                                                    sh_full, eb, wi % kWaves);
+                scan_item<Tile, NQ, WQ, MODE, true, true, true>(A, wi / kWaves, wi / kWaves, sh_val,
+                                                                sh_idx, sh_full, eb, wi % kWaves);
+            flush_pairs<false, Tile::kFused>(A, eb);
             return;
         }
     }
